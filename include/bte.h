@@ -1,0 +1,185 @@
+/*
+ * bte.h -- C ABI of the MI355X (gfx950) phonon Boltzmann transport time step.
+ *
+ * The library advances the non-gray, discrete-ordinates, finite-volume phonon
+ * BTE under the single-relaxation-time approximation (paper Sec. 3.1,
+ * Eq. eq-bte and its finite-volume form Eq. eq-bte-fv):
+ *
+ *   dI_{d,b}/dt + v_b s_d . grad I_{d,b} = (I0_b(T) - I_{d,b}) / tau_b
+ *
+ * for every cell P, direction d and band entry b of a uniform Cartesian mesh,
+ * with first-order upwind face values (Sec. 2.1, the upwind operator),
+ * isothermal and specular/symmetry walls through ghost intensities
+ * (Eq. eq-bdry), and the per-cell temperature recovered from the intensity by
+ * integrating over directions and bands (Sec. 2.2, "first law").  Every step of
+ * that path runs in HIP kernels on the caller's stream; the host only validates,
+ * launches and reads back small control words.
+ *
+ * Conventions shared by every call:
+ *   - cell index P = x + nx*(y + ny*z)   (x fastest); 2D meshes have nz = 1,
+ *     hz is ignored (quantities per unit depth) and s_z is ignored;
+ *   - wall order -x, +x, -y, +y, -z, +z;
+ *   - a wall-face array runs over the two other axes, lower axis fastest:
+ *     +-x walls: y + ny*z;  +-y walls: x + nx*z;  +-z walls: x + nx*y;
+ *   - intensity on the device and in bte_intensity(): [band][direction][cell];
+ *   - every host pointer argument is read during the call only and may be freed
+ *     on return; device memory is owned by the caller (see bte_options).
+ *
+ * Errors: every call returns BTE_OK or a negative status and never aborts.
+ * bte_last_error() gives a thread-local message for the last failure.
+ * Validation failures (BTE_E_INVAL) leave the context untouched.  After
+ * BTE_E_DEVICE only bte_destroy() is valid.  BTE_E_NUMERIC (a cell whose energy
+ * is not positive and finite, or whose temperature inversion fails) names the
+ * cell in the message; the step's results are then not meaningful.
+ * Threading: one context may be used by one thread at a time; distinct
+ * contexts are independent.
+ */
+#ifndef BTE_H
+#define BTE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bte_ctx bte_ctx;
+
+enum bte_status {
+  BTE_OK = 0,
+  BTE_E_INVAL = -1,   /* bad argument or inconsistent input */
+  BTE_E_NOMEM = -2,   /* workspace missing or too small */
+  BTE_E_DEVICE = -3,  /* HIP runtime error; context is poisoned */
+  BTE_E_NUMERIC = -4, /* non-physical state in a cell (message names it) */
+  BTE_E_NOTCONV = -5, /* a step hit max_inner (only if fail_on_notconv) */
+  BTE_E_STATE = -6    /* state buffer of the wrong size */
+};
+
+/* Wall kinds (Eq. eq-bdry).  Specular and symmetry give the same ghost on
+ * axis-aligned walls: the cell's own intensity in the mirrored direction. */
+enum bte_wall { BTE_WALL_ISOTHERMAL = 0, BTE_WALL_SPECULAR = 1, BTE_WALL_SYMMETRY = 2 };
+
+/* Time discretisation.  IMPLICIT_JACOBI: backward Euler, point-Jacobi inner
+ * sweeps, temperature re-inverted after every sweep.  EXPLICIT_EULER: the
+ * paper's forward Euler (Sec. 2.1, Eq. eq-conservation-discrete), temperature
+ * updated once after the step (Sec. 3.2, postStepFunction). */
+enum bte_scheme { BTE_IMPLICIT_JACOBI = 0, BTE_EXPLICIT_EULER = 1 };
+
+/* Storage / arithmetic of the intensity sweep.  FP32_MIXED keeps intensities
+ * and sweep arithmetic in FP32 and the energy reduction, temperature inversion
+ * and residual norms in FP64. */
+enum bte_precision { BTE_FP64 = 0, BTE_FP32_MIXED = 1 };
+
+/* Temperature definition.  TAU_WEIGHTED: W sum_b I0_b(T)/tau_b =
+ * sum_b (1/tau_b) sum_d w_d I_{d,b} (energy-conserving relaxation when tau
+ * varies by band).  ENERGY: W sum_b I0_b(T) = sum_b sum_d w_d I_{d,b}. */
+enum bte_tdef { BTE_T_TAU_WEIGHTED = 0, BTE_T_ENERGY = 1 };
+
+/* Mesh, walls and initial temperature (host arrays). */
+typedef struct {
+  int dim;                  /* 2 or 3 */
+  int n[3];                 /* cells per axis; n[2] = 1 in 2D */
+  double h[3];              /* cell size per axis [m]; h[2] ignored in 2D */
+  int wall[6];              /* bte_wall per side; z sides ignored in 2D */
+  const double* wall_T[6];  /* per-face temperature [K] of isothermal walls, else NULL */
+  const double* T_init;     /* [N_c] initial temperature [K]; I starts at I0_b(T_init) */
+} bte_mesh;
+
+/* Discrete directions (host arrays): unit vectors s[3*d + axis] and solid-angle
+ * weights w[d] [sr].  Specular/symmetry walls need the set to be closed under
+ * the wall's mirror (checked at create). */
+typedef struct {
+  int n;
+  const double* s;
+  const double* w;
+} bte_dirs;
+
+/* Band entries (host arrays): angular frequency omega[b] and band width
+ * domega[b] [rad/s]. */
+typedef struct {
+  int n;
+  const double* omega;
+  const double* domega;
+} bte_bands;
+
+/* Per-band material data (host arrays of length bands->n): group speed vg [m/s],
+ * relaxation time tau [s], density of states per polarisation dos [s/m^3] and
+ * polarisation degeneracy deg.  The equilibrium intensity per steradian is
+ * I0_b(T) = C_b / (exp(hbar omega_b / k_B T) - 1), C_b = deg hbar omega dos domega / (4 pi). */
+typedef struct {
+  const double* vg;
+  const double* tau;
+  const double* dos;
+  const double* deg;
+} bte_dispersion;
+
+typedef struct {
+  double dt;            /* time step [s] > 0 */
+  double tol;           /* inner stop: ||I^{k+1}-I^k|| <= tol ||I^{k+1}-I^n|| */
+  int max_inner;        /* cap on inner sweeps per step (<= 0: 200) */
+  int scheme;           /* bte_scheme */
+  int precision;        /* bte_precision */
+  int t_definition;     /* bte_tdef */
+  int fail_on_notconv;  /* nonzero: a step that hits max_inner returns BTE_E_NOTCONV */
+  int timing;           /* nonzero: time every sweep kernel with HIP events */
+  void* stream;         /* hipStream_t the work is enqueued on (NULL = null stream) */
+  void* workspace;      /* device memory of >= bte_workspace_size() bytes, 256-B aligned,
+                           owned by the caller and kept alive until bte_destroy() */
+  size_t workspace_bytes;
+} bte_options;
+
+typedef struct {
+  int inner;       /* inner sweeps taken (1 in explicit mode) */
+  int converged;   /* 1 if the tolerance (or the requested fixed count) was met */
+  int newton_max;  /* most Newton iterations any cell needed in the step */
+  int reserved;
+  double res;      /* final step-relative increment norm */
+} bte_step_stats;
+
+/* Bytes of device workspace that bte_create() needs for these inputs. */
+int bte_workspace_size(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* bands,
+                       const bte_options* opt, size_t* bytes);
+
+/* Validates and copies every input, derives the mirror maps and the per-(d,b)
+ * coefficients, binds the workspace and stream, and enqueues the initial state
+ * I_{d,b,P} = I0_b(T_init(P)) (Sec. 3.2, initial condition).  On success *out
+ * receives the context. */
+int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* bands,
+               const bte_dispersion* disp, const bte_options* opt, bte_ctx** out);
+
+/* Advances nsteps time steps.  fixed_inner (nullable, [nsteps]): if non-NULL and
+ * fixed_inner[i] > 0, step i takes exactly that many inner sweeps (replays
+ * another solver's schedule); otherwise it stops on tol / max_inner.  stats
+ * (nullable, [nsteps]) receives one record per step.  Returns when the work is
+ * complete on the stream. */
+int bte_step(bte_ctx* ctx, int nsteps, const int* fixed_inner, bte_step_stats* stats);
+
+/* Copies the cell temperatures [N_c] to host memory T_out (n_cells entries). */
+int bte_temperature(bte_ctx* ctx, double* T_out, size_t n_cells);
+
+/* Copies the intensity at the current time level to host memory, FP64,
+ * layout [band][direction][cell]; n = N_b * N_d * N_c. */
+int bte_intensity(bte_ctx* ctx, double* I_out, size_t n);
+
+/* Copies the per-cell energy density E_P = sum_b sum_d w_d I_{d,b,P} [N_c]. */
+int bte_energy(bte_ctx* ctx, double* E_out, size_t n_cells);
+
+/* Replaces the state: intensity (host, FP64, [band][direction][cell]) and
+ * temperature [N_c] (each > 0).  The temperature must be consistent with the
+ * intensity for the result to be meaningful (it seeds the next inversion). */
+int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size_t n_cells);
+
+/* Sum and count of the sweep-kernel durations measured since the last call
+ * (options.timing must be set); resets the accumulators. */
+int bte_sweep_time(bte_ctx* ctx, double* total_ms, int* count);
+
+/* Releases host-side resources (not the caller's workspace). */
+int bte_destroy(bte_ctx* ctx);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* bte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTE_H */

@@ -1,0 +1,254 @@
+"""Python binding of the HIP BTE library (``libbte.so``, C ABI in include/bte.h).
+
+Argument marshalling only: every step of the time step runs in the library's
+HIP kernels.  PyTorch provides the device workspace (a uint8 tensor owned by
+the Solver) and the stream handle; nothing here computes the method.  There is
+no CPU fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbte.so")
+
+BTE_OK = 0
+BTE_E_INVAL = -1
+BTE_E_NOMEM = -2
+BTE_E_DEVICE = -3
+BTE_E_NUMERIC = -4
+BTE_E_NOTCONV = -5
+BTE_E_STATE = -6
+
+BTE_WALL_ISOTHERMAL, BTE_WALL_SPECULAR, BTE_WALL_SYMMETRY = 0, 1, 2
+BTE_IMPLICIT_JACOBI, BTE_EXPLICIT_EULER = 0, 1
+BTE_FP64, BTE_FP32_MIXED = 0, 1
+BTE_T_TAU_WEIGHTED, BTE_T_ENERGY = 0, 1
+
+# every symbol include/bte.h declares
+EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "bte_intensity",
+           "bte_energy", "bte_set_state", "bte_sweep_time", "bte_destroy", "bte_last_error")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class bte_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("wall", C.c_int * 6),
+                ("wall_T", _dp * 6), ("T_init", _dp)]
+
+
+class bte_dirs(C.Structure):
+    _fields_ = [("n", C.c_int), ("s", _dp), ("w", _dp)]
+
+
+class bte_bands(C.Structure):
+    _fields_ = [("n", C.c_int), ("omega", _dp), ("domega", _dp)]
+
+
+class bte_dispersion(C.Structure):
+    _fields_ = [("vg", _dp), ("tau", _dp), ("dos", _dp), ("deg", _dp)]
+
+
+class bte_options(C.Structure):
+    _fields_ = [("dt", C.c_double), ("tol", C.c_double), ("max_inner", C.c_int),
+                ("scheme", C.c_int), ("precision", C.c_int), ("t_definition", C.c_int),
+                ("fail_on_notconv", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
+class bte_step_stats(C.Structure):
+    _fields_ = [("inner", C.c_int), ("converged", C.c_int), ("newton_max", C.c_int),
+                ("reserved", C.c_int), ("res", C.c_double)]
+
+
+class BteError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load the in-tree libbte.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_2305_19400_amd.build.build()")
+    lib = C.CDLL(path)
+    lib.bte_workspace_size.argtypes = [C.POINTER(bte_mesh), C.POINTER(bte_dirs),
+                                       C.POINTER(bte_bands), C.POINTER(bte_options),
+                                       C.POINTER(C.c_size_t)]
+    lib.bte_create.argtypes = [C.POINTER(bte_mesh), C.POINTER(bte_dirs), C.POINTER(bte_bands),
+                               C.POINTER(bte_dispersion), C.POINTER(bte_options),
+                               C.POINTER(C.c_void_p)]
+    lib.bte_step.argtypes = [C.c_void_p, C.c_int, _ip, C.POINTER(bte_step_stats)]
+    lib.bte_temperature.argtypes = [C.c_void_p, _dp, C.c_size_t]
+    lib.bte_intensity.argtypes = [C.c_void_p, _dp, C.c_size_t]
+    lib.bte_energy.argtypes = [C.c_void_p, _dp, C.c_size_t]
+    lib.bte_set_state.argtypes = [C.c_void_p, _dp, C.c_size_t, _dp, C.c_size_t]
+    lib.bte_sweep_time.argtypes = [C.c_void_p, _dp, _ip]
+    lib.bte_destroy.argtypes = [C.c_void_p]
+    lib.bte_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        getattr(lib, name).restype = C.c_char_p if name == "bte_last_error" else C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != BTE_OK:
+        raise BteError(rc, load_library().bte_last_error().decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Inputs:
+    """C structs for one instance; keeps the host arrays alive while in use."""
+
+    def __init__(self, inst, opts: dict):
+        self.keep = []
+
+        def ptr(a):
+            a = _f64(a)
+            self.keep.append(a)
+            return a.ctypes.data_as(_dp)
+
+        m = bte_mesh()
+        m.dim = int(inst.dim)
+        for a in range(3):
+            m.n[a] = int(inst.n[a])
+            m.h[a] = float(inst.h[a])
+        for f in range(6):
+            m.wall[f] = int(inst.wall[f])
+            m.wall_T[f] = ptr(inst.wall_T[f]) if inst.wall_T[f] is not None else _dp()
+        m.T_init = ptr(inst.T_init)
+        d = bte_dirs(int(inst.s.shape[0]), ptr(inst.s), ptr(inst.w))
+        b = bte_bands(int(inst.omega.shape[0]), ptr(inst.omega), ptr(inst.domega))
+        disp = bte_dispersion(ptr(inst.vg), ptr(inst.tau), ptr(inst.dos), ptr(inst.deg))
+        o = bte_options()
+        o.dt = float(opts["dt"])
+        o.tol = float(opts["tol"])
+        o.max_inner = int(opts["max_inner"])
+        o.scheme = int(opts["scheme"])
+        o.precision = int(opts["precision"])
+        o.t_definition = int(opts["t_definition"])
+        o.fail_on_notconv = int(opts.get("fail_on_notconv", 0))
+        o.timing = int(bool(opts.get("timing", False)))
+        self.mesh, self.dirs, self.bands, self.disp, self.opt = m, d, b, disp, o
+
+
+def bte_workspace_size(inst, **opts) -> int:
+    lib = load_library()
+    inp = _Inputs(inst, _resolve(inst, opts))
+    n = C.c_size_t(0)
+    _check(lib.bte_workspace_size(C.byref(inp.mesh), C.byref(inp.dirs), C.byref(inp.bands),
+                                  C.byref(inp.opt), C.byref(n)))
+    return int(n.value)
+
+
+def _resolve(inst, opts: dict) -> dict:
+    out = dict(dt=inst.dt, tol=inst.tol, max_inner=inst.max_inner, scheme=inst.scheme,
+               precision=inst.precision, t_definition=inst.t_definition)
+    out.update({k: v for k, v in opts.items() if v is not None})
+    return out
+
+
+class Solver:
+    """One library context for an input instance, on a torch CUDA device."""
+
+    def __init__(self, inst, device: str = "cuda:0", stream=None, **opts):
+        import torch
+
+        self.lib = load_library()
+        self.inst = inst
+        self.opts = _resolve(inst, opts)
+        self.nc = int(np.prod(inst.n))
+        self.nd = int(inst.s.shape[0])
+        self.nb = int(inst.omega.shape[0])
+        self.device = torch.device(device)
+        inp = _Inputs(inst, self.opts)
+        nbytes = C.c_size_t(0)
+        _check(self.lib.bte_workspace_size(C.byref(inp.mesh), C.byref(inp.dirs),
+                                           C.byref(inp.bands), C.byref(inp.opt),
+                                           C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise BteError(BTE_E_INVAL, "torch workspace is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        inp.opt.stream = C.c_void_p(int(self.stream.cuda_stream))
+        inp.opt.workspace = C.c_void_p(self.workspace.data_ptr())
+        inp.opt.workspace_bytes = int(nbytes.value)
+        self._ctx = C.c_void_p(0)
+        _check(self.lib.bte_create(C.byref(inp.mesh), C.byref(inp.dirs), C.byref(inp.bands),
+                                   C.byref(inp.disp), C.byref(inp.opt), C.byref(self._ctx)))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.workspace.numel())
+
+    def step(self, nsteps: int = 1, fixed_inner: Optional[List[int]] = None) -> List[dict]:
+        st = (bte_step_stats * max(nsteps, 1))()
+        fx = None
+        if fixed_inner is not None:
+            if len(fixed_inner) != nsteps:
+                raise ValueError("fixed_inner needs one entry per step")
+            fx = (C.c_int * nsteps)(*[int(v) for v in fixed_inner])
+        _check(self.lib.bte_step(self._ctx, int(nsteps), fx, st))
+        return [dict(inner=s.inner, converged=s.converged, newton_max=s.newton_max, res=s.res)
+                for s in st[:nsteps]]
+
+    def temperature(self) -> np.ndarray:
+        T = np.empty(self.nc)
+        _check(self.lib.bte_temperature(self._ctx, T.ctypes.data_as(_dp), self.nc))
+        return T
+
+    def energy(self) -> np.ndarray:
+        E = np.empty(self.nc)
+        _check(self.lib.bte_energy(self._ctx, E.ctypes.data_as(_dp), self.nc))
+        return E
+
+    def intensity(self) -> np.ndarray:
+        """Intensity at the current time level, FP64, shape [N_b, N_d, N_c]."""
+        I = np.empty(self.nb * self.nd * self.nc)
+        _check(self.lib.bte_intensity(self._ctx, I.ctypes.data_as(_dp), I.size))
+        return I.reshape(self.nb, self.nd, self.nc)
+
+    def set_state(self, I: np.ndarray, T: np.ndarray):
+        I = _f64(I).reshape(-1)
+        T = _f64(T).reshape(-1)
+        _check(self.lib.bte_set_state(self._ctx, I.ctypes.data_as(_dp), I.size,
+                                      T.ctypes.data_as(_dp), T.size))
+
+    def sweep_time(self):
+        """(total ms, count) of sweep kernels timed since the last call."""
+        ms = C.c_double(0.0)
+        n = C.c_int(0)
+        _check(self.lib.bte_sweep_time(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self.lib.bte_destroy(self._ctx)
+            self._ctx = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

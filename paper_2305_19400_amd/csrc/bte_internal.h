@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernels and the C-ABI host code of the
+// BTE library.  Not installed; the public interface is include/bte.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace bte {
+
+// CODATA 2018 values.
+constexpr double kHbar = 1.054571817e-34;  // J s
+constexpr double kBoltzmann = 1.380649e-23;  // J / K
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr int kNewtonMaxIters = 50;
+constexpr double kNewtonAcceptRel = 1e-14;
+constexpr double kNewtonStepRel = 1e-13;
+
+constexpr int kSweepBlock = 256;     // threads per sweep workgroup (4 waves)
+constexpr int kCellBlock = 256;      // threads per per-cell kernel workgroup
+constexpr int kReduceBlock = 256;    // threads of the single-workgroup reductions
+constexpr int kSlabAlign = 64;       // cells per slab rounded up to this
+
+// Control words of the inner iteration, written by the device, mirrored to the host.
+struct Control {
+  int converged;   // inner loop finished (later kernels of the step are no-ops)
+  int k;           // sweeps completed in the current step
+  int newton_max;  // most Newton iterations in any cell this step
+  int err_cell;    // smallest failing cell index, INT_MAX if none
+  double res;      // last step-relative increment norm
+  double num;      // last ||I^{k+1} - I^k||^2
+  double den;      // last ||I^{k+1} - I^n||^2
+};
+
+// Per (band, direction) sweep coefficients: c[a] = v_b |s_{d,a}| / h_a and the
+// update scale (1 / diagonal for Jacobi, dt for forward Euler).
+struct Coef {
+  double c[3];
+  double scale;
+};
+
+// Direction flags: bit a set if s_{d,a} > 0, bit (4 + a) set if s_{d,a} < 0.
+__host__ __device__ inline bool dir_pos(int flags, int a) { return (flags >> a) & 1; }
+__host__ __device__ inline bool dir_neg(int flags, int a) { return (flags >> (4 + a)) & 1; }
+
+struct Geometry {
+  int dim;
+  int nx, ny, nz;
+  int nc;    // cells
+  int ncp;   // padded cells per slab
+  int nd, nb;
+  double vol;
+};
+
+struct Tables {
+  const Coef* coef;          // [nb][nd]
+  const int* dflags;         // [nd]
+  const int* mirror;         // [3][nd]
+  const double* w;           // [nd]
+  const double* Cb;          // [nb] equilibrium prefactor
+  const double* xfac;        // [nb] hbar omega / k_B
+  const double* inv_tau;     // [nb]
+  const double* fweight;     // [nb] band weight of the temperature relation
+  double W;                  // sum of the direction weights
+  int wall[6];
+  const double* wall_I0[6];  // [nb][nfaces] for isothermal walls, else null
+  int wall_nf[6];
+};
+
+// Launchers (bte_kernels.hip).  All enqueue on `stream` and return the launch status.
+template <typename Real>
+hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t, double inv_dt,
+                        const Real* Ik, const Real* In, Real* Iout, const double* I0, double* S,
+                        double* part, const Control* ctl);
+
+hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
+                              const double* S, double* T, double* I0, double* E, Control* ctl);
+
+hipError_t launch_control(hipStream_t stream, int nparts, const double* part, double vol,
+                          int fixed_k, int max_inner, double tol, int explicit_mode,
+                          Control* ctl);
+
+hipError_t launch_reset(hipStream_t stream, Control* ctl);
+
+hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Tables& t,
+                              const double* T, double* I0, double* E);
+
+hipError_t launch_wall_table(hipStream_t stream, int nb, int nf, const double* Cb,
+                             const double* xfac, const double* wallT, double* out);
+
+template <typename Real>
+hipError_t launch_broadcast(hipStream_t stream, const Geometry& g, const double* I0, Real* I);
+
+template <typename Real>
+hipError_t launch_energy(hipStream_t stream, const Geometry& g, const Tables& t, const Real* I,
+                         double* E);
+
+}  // namespace bte

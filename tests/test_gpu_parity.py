@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Bar: FP64 mode within 1e-10 relative, element by element, in T and in every
+intensity.  Inner-iteration counts are data dependent, so the GPU replays the
+oracle's per-step schedule (two correct solvers may stop one sweep apart when
+the residual sits within round-off of the tolerance); free-running counts are
+checked to agree as well.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2305_19400_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_19400_amd import bte
+    bte.load_library()
+    return bte
+
+
+def oracle_for(inst, **kw):
+    from oracle import Oracle
+    return Oracle(inst, **kw)
+
+
+def to_gpu_layout(I_oracle):
+    return np.ascontiguousarray(I_oracle.transpose(2, 1, 0))  # [P][d][b] -> [b][d][P]
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(gpu, inst, nsteps, replay=True, **opts):
+    ref = oracle_for(inst, **{k: v for k, v in opts.items() if k in ("scheme", "t_definition", "tol", "dt")})
+    ref_st = ref.run(nsteps)
+    sched = [s["inner"] for s in ref_st]
+    announce(f"{inst.name} n={inst.n} nd={inst.n_dirs} nb={inst.n_bands} steps={nsteps} sched={sched} opts={opts}")
+    with gpu.Solver(inst, **opts) as sol:
+        st = sol.step(nsteps, fixed_inner=sched if replay else None)
+        T, Iq = sol.temperature(), sol.intensity()
+    return ref, ref_st, st, T, Iq
+
+
+def ragged_2d(seed=31):
+    rng = np.random.default_rng(seed)
+    inst = I.strip_2d(37, 29, 2, 8, 4, seed=seed, strip_cells=6, nsteps=5)
+    inst.T_init[:] = rng.uniform(295.0, 320.0, inst.n_cells)
+    inst.wall_T[2] = rng.uniform(298.0, 305.0, inst.wall_T[2].shape)
+    inst.name = "ragged2d_37x29"
+    return inst
+
+
+def ragged_3d(seed=41):
+    rng = np.random.default_rng(seed)
+    inst = I.gaussian_3d(9, 7, 5, 2, 8, 3, seed=seed, sigma_cells=2.0, peak=30.0,
+                         precision=I.PRECISION_FP64, nsteps=3)
+    inst.wall = [0, 1, 2, 0, 1, 0]
+    inst.wall_T = [None if inst.wall[f] != 0 else rng.uniform(296.0, 306.0, inst.wall_face_count(f))
+                   for f in range(6)]
+    inst.h = [1e-8, 1.3e-8, 0.8e-8]
+    inst.name = "ragged3d_9x7x5"
+    return inst
+
+
+# ---------------------------------------------------------------- parity
+def test_c1_full_parity(gpu):
+    inst = I.config_c1()
+    ref, ref_st, st, T, Iq = run_pair(gpu, inst, inst.nsteps)
+    assert [s["inner"] for s in st] == [s["inner"] for s in ref_st]
+    assert rel(T, ref.temperature()) <= TOL
+    assert rel(Iq, to_gpu_layout(ref.intensity())) <= TOL
+    for a, b in zip(st, ref_st):
+        assert abs(a["res"] - b["res"]) <= 1e-8 * b["res"] + 1e-300
+
+
+def test_c1_free_running_matches_schedule(gpu):
+    inst = I.config_c1()
+    ref = oracle_for(inst)
+    ref_st = ref.run(inst.nsteps)
+    announce("c1 free-running")
+    with gpu.Solver(inst) as sol:
+        st = sol.step(inst.nsteps)
+        T = sol.temperature()
+    assert [s["inner"] for s in st] == [s["inner"] for s in ref_st]
+    assert all(s["converged"] for s in st)
+    assert rel(T, ref.temperature()) <= TOL
+
+
+@pytest.mark.parametrize("maker", [ragged_2d, ragged_3d])
+def test_ragged_parity(gpu, maker):
+    inst = maker()
+    ref, ref_st, st, T, Iq = run_pair(gpu, inst, inst.nsteps)
+    assert rel(T, ref.temperature()) <= TOL
+    assert rel(Iq, to_gpu_layout(ref.intensity())) <= TOL
+    assert np.max(np.abs(T - inst.T_init)) > 1e-3
+
+
+@pytest.mark.parametrize("maker", [ragged_2d, ragged_3d])
+def test_explicit_parity(gpu, maker):
+    inst = maker()
+    inst.dt = 2e-13  # within the forward-Euler stability limit
+    ref, ref_st, st, T, Iq = run_pair(gpu, inst, 6, scheme=I.SCHEME_EXPLICIT_EULER, dt=2e-13)
+    assert all(s["inner"] == 1 for s in st)
+    assert rel(T, ref.temperature()) <= TOL
+    assert rel(Iq, to_gpu_layout(ref.intensity())) <= TOL
+
+
+def test_energy_definition_parity(gpu):
+    inst = ragged_2d(seed=5)
+    ref, ref_st, st, T, Iq = run_pair(gpu, inst, 3, t_definition=I.TDEF_ENERGY)
+    assert rel(T, ref.temperature()) <= TOL
+    assert rel(Iq, to_gpu_layout(ref.intensity())) <= TOL
+
+
+def test_c2_downscaled_full_angular_spectral(gpu):
+    """C2's full 400 directions x 55 band entries on a 32 x 32 mesh (several
+    tiles per band), strip heater, specular sides."""
+    inst = I.strip_2d(32, 32, 20, 20, 40, seed=2, nsteps=3)
+    ref, ref_st, st, T, Iq = run_pair(gpu, inst, 3)
+    assert rel(T, ref.temperature()) <= TOL
+    assert rel(Iq, to_gpu_layout(ref.intensity())) <= TOL
+    assert T.max() > 300.0 + 1e-3
+
+
+def test_c2_full_size_first_step(gpu):
+    """Full C2 (128 x 128 x 400 x 55, the benchmarked configuration): one time
+    step replaying the oracle's inner count; every temperature and a seeded
+    sample of 200k intensities compared."""
+    inst = I.config_c2()
+    ref = oracle_for(inst)
+    k = ref.step()["inner"]
+    T_ref = ref.temperature()
+    I_ref = ref.intensity()  # [P][d][b]
+    announce(f"c2 full size, one step, k={k}")
+    with gpu.Solver(inst) as sol:
+        st = sol.step(1, fixed_inner=[k])
+        T = sol.temperature()
+        Iq = sol.intensity()
+    assert rel(T, T_ref) <= TOL
+    rng = np.random.default_rng(0)
+    n = 200_000
+    P = rng.integers(0, inst.n_cells, n)
+    d = rng.integers(0, inst.n_dirs, n)
+    b = rng.integers(0, inst.n_bands, n)
+    assert rel(Iq[b, d, P], I_ref[P, d, b]) <= TOL
+    # the hot strip's wall cells are sampled too
+    top = (inst.n[1] - 1) * inst.n[0] + np.arange(inst.n[0])
+    assert rel(Iq[:, :, top], to_gpu_layout(I_ref[top])) <= TOL
+
+
+# ---------------------------------------------------------------- invariants on the device
+@pytest.mark.parametrize("kinds", [(0, 0, 0, 0), (1, 2, 1, 1)])
+def test_uniform_state_bitwise_invariant(gpu, kinds):
+    inst = ragged_2d()
+    inst.wall = list(kinds) + [0, 0]
+    inst.wall_T = I.uniform_walls(inst.n, 2, inst.wall, [300.0] * 6)
+    inst.T_init[:] = 300.0
+    announce(f"uniform invariance walls={kinds}")
+    with gpu.Solver(inst) as sol:
+        I0, T0 = sol.intensity(), sol.temperature()
+        st = sol.step(4)
+        assert np.array_equal(sol.intensity(), I0)
+        assert np.array_equal(sol.temperature(), T0)
+    assert all(s["inner"] == 1 for s in st)
+
+
+def test_adiabatic_box_conserves_energy(gpu):
+    inst = ragged_2d(seed=9)
+    inst.wall = [1, 2, 1, 1, 0, 0]
+    inst.wall_T = [None] * 6
+    announce("adiabatic specular box, explicit")
+    with gpu.Solver(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=1e-13) as sol:
+        V = inst.h[0] * inst.h[1]
+        E0 = V * sol.energy().sum()
+        sol.step(20)
+        E1 = V * sol.energy().sum()
+        T = sol.temperature()
+    assert abs(E1 - E0) / E0 < 1e-13
+    assert T.max() - T.min() < inst.T_init.max() - inst.T_init.min()
+
+
+def test_deterministic_bitwise(gpu):
+    inst = ragged_3d()
+    out = []
+    announce("determinism: two identical runs")
+    for _ in range(2):
+        with gpu.Solver(inst) as sol:
+            sol.step(2)
+            out.append((sol.intensity(), sol.temperature()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_set_state_round_trip(gpu):
+    inst = ragged_2d(seed=17)
+    announce("set_state round trip")
+    with gpu.Solver(inst) as a, gpu.Solver(inst) as b:
+        a.step(2)
+        b.set_state(a.intensity(), a.temperature())
+        sa = a.step(2)
+        sb = b.step(2)
+        assert [s["inner"] for s in sa] == [s["inner"] for s in sb]
+        assert np.array_equal(a.intensity(), b.intensity())
+        assert np.array_equal(a.temperature(), b.temperature())
+
+
+# ---------------------------------------------------------------- failure handling (forced from the host)
+def test_numeric_failure_names_cell(gpu):
+    inst = ragged_2d(seed=3)
+    announce("forced numeric failure")
+    with gpu.Solver(inst) as sol:
+        Iq = sol.intensity()
+        T = sol.temperature()
+        bad = 123
+        Iq[:, :, bad] = -1e12  # no positive energy can come out of this cell
+        sol.set_state(Iq, T)
+        with pytest.raises(gpu.BteError) as e:
+            sol.step(1)
+        assert e.value.code == gpu.BTE_E_NUMERIC
+        assert f"cell {bad}" in str(e.value)
+
+
+def test_not_converged_reported(gpu):
+    inst = ragged_2d(seed=4)
+    announce("forced non-convergence")
+    with gpu.Solver(inst, tol=1e-15, max_inner=2, fail_on_notconv=1) as sol:
+        with pytest.raises(gpu.BteError) as e:
+            sol.step(1)
+        assert e.value.code == gpu.BTE_E_NOTCONV
+    with gpu.Solver(inst, tol=1e-15, max_inner=2) as sol:
+        st = sol.step(1)
+        assert st[0]["inner"] == 2 and not st[0]["converged"]
+
+
+def test_sweep_timing_counts_sweeps(gpu):
+    inst = I.config_c1()
+    announce("sweep timing")
+    with gpu.Solver(inst, timing=True) as sol:
+        st = sol.step(3)
+        ms, n = sol.sweep_time()
+    assert n == sum(s["inner"] for s in st)
+    assert ms > 0.0
