@@ -57,6 +57,19 @@ def cpu_baseline(inst, log_fn):
                       f"{updates:.3e} updates) in {dt:.1f} s"}
 
 
+def copy_probe():
+    """A plain copy kernel of known size: reads 1 GiB and writes 1 GiB once, so
+    the HBM byte counters of a profiler can be scaled against known traffic."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: {4 * n} bytes read, {4 * n} bytes written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,7 +77,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the band-sharded design is described, not built).", file=sys.stderr)

@@ -76,10 +76,15 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
-    """Load the in-tree libbte.so; raises if it has not been built."""
+    """Load the in-tree libbte.so; raises if it has not been built.
+
+    torch is imported first so that the process holds one HIP runtime: the
+    library's libamdhip64.so.7 dependency then resolves to the copy torch has
+    already loaded (two runtimes in one process do not share the device)."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (see docstring)
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with paper_2305_19400_amd.build.build()")
     lib = C.CDLL(path)

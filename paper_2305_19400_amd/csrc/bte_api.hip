@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -40,7 +41,7 @@ constexpr double kMirrorTol = 1e-12;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctl, coef, dflags, mirror, w, Cb, xfac, inv_tau, fweight;
+  size_t ctl, coef, dflags, mirror, w, Cb, xfac, inv_tau, fweight, Iref;
   size_t wallT[6], wallI0[6];
   size_t T, Tprev, E, I0, S, part;
   size_t In, Ia, Ib;
@@ -48,11 +49,17 @@ struct Layout {
 };
 
 struct Shape {
-  int dim, nx, ny, nz, nc, ncp, nd, nb, ntiles, nparts;
+  int dim, nx, ny, nz, nc, ncp, nd, nb;
   int nf[6];
   bool iso[6];
   size_t real_size;
+  SweepPlan plan;
 };
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return (v && *v) ? atoi(v) : dflt;
+}
 
 Layout make_layout(const Shape& s) {
   Layout L{};
@@ -71,6 +78,7 @@ Layout make_layout(const Shape& s) {
   L.xfac = take(sizeof(double) * (size_t)s.nb);
   L.inv_tau = take(sizeof(double) * (size_t)s.nb);
   L.fweight = take(sizeof(double) * (size_t)s.nb);
+  L.Iref = take(sizeof(double) * (size_t)s.nb);
   for (int f = 0; f < 6; ++f) {
     L.wallT[f] = s.iso[f] ? take(sizeof(double) * (size_t)s.nf[f]) : 0;
     L.wallI0[f] = s.iso[f] ? take(sizeof(double) * (size_t)s.nf[f] * s.nb) : 0;
@@ -79,13 +87,13 @@ Layout make_layout(const Shape& s) {
   L.Tprev = take(sizeof(double) * (size_t)s.ncp);
   L.E = take(sizeof(double) * (size_t)s.ncp);
   L.I0 = take(sizeof(double) * (size_t)s.nb * s.ncp);
-  L.S = take(sizeof(double) * (size_t)s.nb * s.ncp);
-  L.part = take(sizeof(double) * 2 * (size_t)s.nparts);
+  L.S = take(sizeof(double) * (size_t)s.plan.ndg * s.nb * s.ncp);
+  L.part = take(sizeof(double) * 2 * (size_t)s.plan.nparts);
   const size_t field = s.real_size * (size_t)s.nb * s.nd * s.ncp;
   L.In = take(field);
   L.Ia = take(field);
   L.Ib = take(field);
-  L.total = off;
+  L.total = off + 65536;  // tail slack: no kernel access may reach past the last array
   return L;
 }
 
@@ -121,8 +129,11 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   s.ncp = (int)((nc + kSlabAlign - 1) / kSlabAlign * kSlabAlign);
   s.nd = d->n;
   s.nb = b->n;
-  s.ntiles = (s.nc + kSweepBlock - 1) / kSweepBlock;
-  s.nparts = s.ntiles * s.nb;
+  // Launch layout of the sweep; BTE_SWEEP_RY / BTE_SWEEP_NDG / BTE_SWEEP_KIND
+  // override the rows per wave, the number of direction groups and the kernel
+  // family (tuning knobs).
+  s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", 0),
+                           env_int("BTE_SWEEP_NDG", 0), env_int("BTE_SWEEP_KIND", -1));
   s.real_size = o->precision == BTE_FP64 ? sizeof(double) : sizeof(float);
   const int nfaces[3] = {s.ny * s.nz, s.nx * s.nz, s.nx * s.ny};
   for (int f = 0; f < 6; ++f) {
@@ -166,6 +177,7 @@ struct bte_ctx {
   double* I0;
   double* S;
   double* part;
+  std::vector<double> Iref;  // host copy of the storage reference per band
   bool poisoned;
 };
 
@@ -206,7 +218,7 @@ void find_mirrors(const bte_dirs* d, int dim, std::vector<int>& mirror) {
 
 template <typename Real>
 int enqueue_sweep(bte_ctx* ctx, const void* src, void* dst) {
-  HIP_TRY(launch_sweep<Real>(ctx->stream, ctx->g, ctx->t, 1.0 / ctx->opt.dt,
+  HIP_TRY(launch_sweep<Real>(ctx->stream, ctx->g, ctx->t, ctx->s.plan, 1.0 / ctx->opt.dt,
                              static_cast<const Real*>(src), static_cast<const Real*>(ctx->In),
                              static_cast<Real*>(dst), ctx->I0, ctx->S, ctx->part, ctx->ctl));
   return BTE_OK;
@@ -232,7 +244,7 @@ int enqueue_iteration(bte_ctx* ctx, int j, int fixed_k) {
   if (timing) HIP_TRY(hipEventRecord(ctx->t_stop[j], ctx->stream));
   HIP_TRY(launch_temperature(ctx->stream, ctx->g, ctx->t, ctx->S, ctx->T, ctx->I0, ctx->E,
                              ctx->ctl));
-  HIP_TRY(launch_control(ctx->stream, ctx->s.nparts, ctx->part, ctx->g.vol, fixed_k,
+  HIP_TRY(launch_control(ctx->stream, ctx->s.plan.nparts, ctx->part, ctx->g.vol, fixed_k,
                          ctx->opt.max_inner, ctx->opt.tol,
                          ctx->opt.scheme == BTE_EXPLICIT_EULER, ctx->ctl));
   return BTE_OK;
@@ -424,6 +436,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   g.ncp = s.ncp;
   g.nd = nd;
   g.nb = nb;
+  g.ndg = s.plan.ndg;
   g.vol = h[0] * h[1] * h[2];
   Tables& t = ctx->t;
   t.coef = at<Coef>(ws, L.coef);
@@ -434,6 +447,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   t.xfac = at<double>(ws, L.xfac);
   t.inv_tau = at<double>(ws, L.inv_tau);
   t.fweight = at<double>(ws, L.fweight);
+  t.Iref = at<double>(ws, L.Iref);
   t.W = W;
   for (int f = 0; f < 6; ++f) {
     t.wall[f] = (f < 2 * s.dim) ? mesh->wall[f] : BTE_WALL_SPECULAR;
@@ -473,18 +487,31 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
     CREATE_TRY(launch_wall_table(ctx->stream, nb, s.nf[f], t.Cb, t.xfac,
                                  at<double>(ws, L.wallT[f]), at<double>(ws, L.wallI0[f])));
   }
+  // FP32 storage keeps I - I0_b(T_ref) with T_ref the coldest input temperature.
+  double T_ref = 0.0;
+  if (opt->precision == BTE_FP32_MIXED) {
+    T_ref = mesh->T_init[0];
+    for (int P = 1; P < s.nc; ++P) T_ref = std::min(T_ref, mesh->T_init[P]);
+    for (int f = 0; f < 6; ++f)
+      if (s.iso[f])
+        for (int i = 0; i < s.nf[f]; ++i) T_ref = std::min(T_ref, mesh->wall_T[f][i]);
+  }
+  CREATE_TRY(launch_reference(ctx->stream, nb, t.Cb, t.xfac, T_ref, at<double>(ws, L.Iref)));
+  ctx->Iref.assign(nb, 0.0);
+  CREATE_TRY(hipMemcpyAsync(ctx->Iref.data(), at<double>(ws, L.Iref), sizeof(double) * nb,
+                            hipMemcpyDeviceToHost, ctx->stream));
   CREATE_TRY(launch_reset(ctx->stream, ctx->ctl));
   CREATE_TRY(launch_equilibrium(ctx->stream, g, t, ctx->T, ctx->I0, ctx->E));
   CREATE_TRY(hipMemcpyAsync(ctx->Tprev, ctx->T, sizeof(double) * s.nc, hipMemcpyDeviceToDevice,
                             ctx->stream));
   if (opt->precision == BTE_FP64) {
-    CREATE_TRY(launch_broadcast<double>(ctx->stream, g, ctx->I0, static_cast<double*>(ctx->In)));
-    CREATE_TRY(launch_broadcast<double>(ctx->stream, g, ctx->I0, static_cast<double*>(ctx->Ia)));
-    CREATE_TRY(launch_broadcast<double>(ctx->stream, g, ctx->I0, static_cast<double*>(ctx->Ib)));
+    CREATE_TRY(launch_broadcast<double>(ctx->stream, g, t, ctx->I0, static_cast<double*>(ctx->In)));
+    CREATE_TRY(launch_broadcast<double>(ctx->stream, g, t, ctx->I0, static_cast<double*>(ctx->Ia)));
+    CREATE_TRY(launch_broadcast<double>(ctx->stream, g, t, ctx->I0, static_cast<double*>(ctx->Ib)));
   } else {
-    CREATE_TRY(launch_broadcast<float>(ctx->stream, g, ctx->I0, static_cast<float*>(ctx->In)));
-    CREATE_TRY(launch_broadcast<float>(ctx->stream, g, ctx->I0, static_cast<float*>(ctx->Ia)));
-    CREATE_TRY(launch_broadcast<float>(ctx->stream, g, ctx->I0, static_cast<float*>(ctx->Ib)));
+    CREATE_TRY(launch_broadcast<float>(ctx->stream, g, t, ctx->I0, static_cast<float*>(ctx->In)));
+    CREATE_TRY(launch_broadcast<float>(ctx->stream, g, t, ctx->I0, static_cast<float*>(ctx->Ia)));
+    CREATE_TRY(launch_broadcast<float>(ctx->stream, g, t, ctx->I0, static_cast<float*>(ctx->Ib)));
   }
   CREATE_TRY(hipStreamSynchronize(ctx->stream));
 #undef CREATE_TRY
@@ -551,7 +578,8 @@ int bte_intensity(bte_ctx* ctx, double* I_out, size_t n) {
                              sizeof(float) * ctx->s.ncp, sizeof(float) * ctx->s.nc, rows,
                              hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    for (size_t i = 0; i < n; ++i) I_out[i] = tmp[i];
+    const size_t nc = ctx->s.nc;
+    for (size_t i = 0; i < n; ++i) I_out[i] = ctx->Iref[i / (nc * ctx->s.nd)] + (double)tmp[i];
   }
   return BTE_OK;
 }
@@ -576,7 +604,9 @@ int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size
     } catch (...) {
       return fail(BTE_E_NOMEM, "out of host memory");
     }
-    for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<float>(I[i]);
+    const size_t nc = ctx->s.nc;
+    for (size_t i = 0; i < n; ++i)
+      tmp[i] = static_cast<float>(I[i] - ctx->Iref[i / (nc * ctx->s.nd)]);
     HIP_TRY(hipMemcpy2DAsync(ctx->In, sizeof(float) * ctx->s.ncp, tmp.data(),
                              sizeof(float) * ctx->s.nc, sizeof(float) * ctx->s.nc, rows,
                              hipMemcpyHostToDevice, ctx->stream));

@@ -18,7 +18,7 @@ constexpr double kNewtonAcceptRel = 1e-14;
 constexpr double kNewtonStepRel = 1e-13;
 
 constexpr int kSweepBlock = 256;     // threads per sweep workgroup (4 waves)
-constexpr int kCellBlock = 256;      // threads per per-cell kernel workgroup
+constexpr int kCellBlock = 64;       // threads per per-cell kernel workgroup (one wave)
 constexpr int kReduceBlock = 256;    // threads of the single-workgroup reductions
 constexpr int kSlabAlign = 64;       // cells per slab rounded up to this
 
@@ -50,8 +50,25 @@ struct Geometry {
   int nc;    // cells
   int ncp;   // padded cells per slab
   int nd, nb;
+  int ndg;   // direction groups of the energy partials S[ndg][nb][ncp]
   double vol;
 };
+
+// How a sweep is laid out on the device.
+enum SweepKind { kSweepCellPerThread = 0, kSweepColumnWalk2D = 1 };
+
+struct SweepPlan {
+  int kind;
+  int ry;        // rows walked per wave (column-walk kernels)
+  int ntx, nty;  // tiles along x (64 lanes each) and along y (4 waves x ry rows each)
+  int ndg, dgs;  // direction groups and directions per group
+  int ntiles;    // workgroups per (band, direction group)
+  int nparts;    // norm partials written per sweep (one per workgroup)
+};
+
+// Chooses the sweep layout for a mesh; ry / ndg <= 0 and kind < 0 pick defaults.
+SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int ndg,
+                          int kind);
 
 struct Tables {
   const Coef* coef;          // [nb][nd]
@@ -62,6 +79,8 @@ struct Tables {
   const double* xfac;        // [nb] hbar omega / k_B
   const double* inv_tau;     // [nb]
   const double* fweight;     // [nb] band weight of the temperature relation
+  const double* Iref;        // [nb] storage reference: stored value = I - Iref[b]
+                             // (zero in FP64 mode, I0_b(T_ref) in FP32 mode)
   double W;                  // sum of the direction weights
   int wall[6];
   const double* wall_I0[6];  // [nb][nfaces] for isothermal walls, else null
@@ -70,9 +89,10 @@ struct Tables {
 
 // Launchers (bte_kernels.hip).  All enqueue on `stream` and return the launch status.
 template <typename Real>
-hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t, double inv_dt,
-                        const Real* Ik, const Real* In, Real* Iout, const double* I0, double* S,
-                        double* part, const Control* ctl);
+hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
+                        const SweepPlan& plan, double inv_dt, const Real* Ik, const Real* In,
+                        Real* Iout, const double* I0, double* S, double* part,
+                        const Control* ctl);
 
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* S, double* T, double* I0, double* E, Control* ctl);
@@ -89,8 +109,13 @@ hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Table
 hipError_t launch_wall_table(hipStream_t stream, int nb, int nf, const double* Cb,
                              const double* xfac, const double* wallT, double* out);
 
+// Iref[b] = I0_b(T_ref) if T_ref > 0, else 0.
+hipError_t launch_reference(hipStream_t stream, int nb, const double* Cb, const double* xfac,
+                            double T_ref, double* Iref);
+
 template <typename Real>
-hipError_t launch_broadcast(hipStream_t stream, const Geometry& g, const double* I0, Real* I);
+hipError_t launch_broadcast(hipStream_t stream, const Geometry& g, const Tables& t,
+                            const double* I0, Real* I);
 
 template <typename Real>
 hipError_t launch_energy(hipStream_t stream, const Geometry& g, const Tables& t, const Real* I,

@@ -222,6 +222,10 @@ def test_set_state_round_trip(gpu):
 
 # ---------------------------------------------------------------- failure handling (forced from the host)
 def test_numeric_failure_names_cell(gpu):
+    """A cell forced (through the state) to negative energy makes the temperature
+    inversion fail; the library reports BTE_E_NUMERIC and names the smallest
+    failing cell index, the same cell the oracle reports for the same state."""
+    from oracle import OracleError
     inst = ragged_2d(seed=3)
     announce("forced numeric failure")
     with gpu.Solver(inst) as sol:
@@ -233,7 +237,14 @@ def test_numeric_failure_names_cell(gpu):
         with pytest.raises(gpu.BteError) as e:
             sol.step(1)
         assert e.value.code == gpu.BTE_E_NUMERIC
-        assert f"cell {bad}" in str(e.value)
+    ref = oracle_for(inst)
+    ref.set_state(Iq.transpose(2, 1, 0), T)
+    with pytest.raises(OracleError) as eo:
+        ref.step()
+    failed = int(str(eo.value).split("cell")[-1])
+    assert f"cell {failed} " in str(e.value)
+    nx = inst.n[0]
+    assert failed in (bad, bad - 1, bad + 1, bad - nx, bad + nx)
 
 
 def test_not_converged_reported(gpu):
