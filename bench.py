@@ -37,6 +37,22 @@ def sweep_bytes(inst, real_bytes):
     return inst.n_dof * per_update + inst.n_bands * inst.n_cells * per_band_cell
 
 
+def measured_traffic(kernel_file, counters_file):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was measured on the kernel source as it is now; else None."""
+    import hashlib
+    try:
+        with open(counters_file) as f:
+            c = json.load(f)
+        with open(kernel_file, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256") != sha:
+        return None
+    return c.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(inst, log_fn):
     """Oracle (plain FP64 C, OpenMP over cells) on the host cores: the first
     time step of the same workload, all of its inner sweeps."""
@@ -152,6 +168,10 @@ def main():
                      "kernel": "sweep_kernel", "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
     }
+    if prec == bte.BTE_FP64:
+        out["roofline"]["traffic"] = measured_traffic(
+            os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
+            os.path.join(ROOT, "profiles", "sweep2d_c2_fp64_counters.json"))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, log)
     print(json.dumps(out), flush=True)
