@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+                    help="c2 (default, the benchmarked 2D case) or the 3D cases")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -107,7 +109,7 @@ def main():
     import torch
     from paper_2305_19400_amd import bte, inputs
 
-    inst = inputs.config_c2()
+    inst = inputs.CONFIGS[args.workload]()
     prec = bte.BTE_FP64 if args.precision == "fp64" else bte.BTE_FP32_MIXED
     real_bytes = 8 if prec == bte.BTE_FP64 else 4
     dev = torch.device("cuda:0")
@@ -154,7 +156,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == bte.BTE_FP64 else "f32+f64",
         "data": "synthetic (seeded Si-like band tables, strip heater)",
-        "config": {"workload": inst.name, "mesh": "128x128", "dirs": inst.n_dirs,
+        "config": {"workload": inst.name, "mesh": "x".join(str(v) for v in inst.n[:inst.dim]),
+                   "dirs": inst.n_dirs,
                    "bands": inst.n_bands, "dt_s": inst.dt, "tol": inst.tol,
                    "scheme": "implicit backward Euler, point-Jacobi",
                    "time_steps": args.steps},
@@ -168,11 +171,11 @@ def main():
                      "kernel": "sweep_kernel", "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
     }
-    if prec == bte.BTE_FP64:
+    if prec == bte.BTE_FP64 and args.workload == "c2":
         out["roofline"]["traffic"] = measured_traffic(
             os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
             os.path.join(ROOT, "profiles", "sweep2d_c2_fp64_counters.json"))
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(inst, log)
     print(json.dumps(out), flush=True)
 

@@ -126,14 +126,32 @@ typedef struct {
   void* workspace;      /* device memory of >= bte_workspace_size() bytes, 256-B aligned,
                            owned by the caller and kept alive until bte_destroy() */
   size_t workspace_bytes;
+  /* Learned warm start of the next temperature (not in the paper; a
+     perceptron on bf16 matrix cores, trained on the device from the solver's
+     own steps).  The inner iteration still runs to the same tolerance and
+     judges the guess; an implausible guess in a cell falls back to T_n. */
+  int warm_start;       /* BTE_WARM_NONE / BTE_WARM_T / BTE_WARM_T_SHIFT */
+  int nn_train_steps;   /* plain steps recorded before training (<= 0: 20) */
+  int nn_epochs;        /* passes over the recorded samples (<= 0: 2) */
+  float nn_lr;          /* Adam learning rate (<= 0: 1e-3) */
+  unsigned long long nn_seed;  /* initial-weight seed (SplitMix64 counter stream) */
 } bte_options;
+
+/* Warm-start modes.  T: the first sweep of a step uses I0 at the guessed
+ * temperature.  T_SHIFT: additionally starts the intensity from
+ * I^n + I0_b(T_guess) - I0_b(T_n) (an isotropic shift), fused into the first
+ * sweep. */
+enum bte_warm { BTE_WARM_NONE = 0, BTE_WARM_T = 1, BTE_WARM_T_SHIFT = 2 };
 
 typedef struct {
   int inner;       /* inner sweeps taken (1 in explicit mode) */
   int converged;   /* 1 if the tolerance (or the requested fixed count) was met */
   int newton_max;  /* most Newton iterations any cell needed in the step */
-  int reserved;
+  int warm;        /* 1 if the step started from the network's guess */
   double res;      /* final step-relative increment norm */
+  int fallbacks;   /* cells whose guess was rejected in this step */
+  int trained;     /* 1 if the network was trained at the end of this step */
+  double nn_loss;  /* last training minibatch loss (normalised units), if trained */
 } bte_step_stats;
 
 /* Bytes of device workspace that bte_create() needs for these inputs. */
@@ -172,6 +190,30 @@ int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size
 /* Sum and count of the sweep-kernel durations measured since the last call
  * (options.timing must be set); resets the accumulators. */
 int bte_sweep_time(bte_ctx* ctx, double* total_ms, int* count);
+
+/* Learned warm start.  The parameter vector (FP32) is, in order:
+ * W1[128][KP] | b1[128] | W2[128][128] | b2[128] | w3[128] | b3, 3 zeros |
+ * mu_T, s_T, mu_E, s_E, s_D, 3 zeros
+ * with KP = 32 (2D) or 96 (3D) input features (27 or 81 used, the rest zero).
+ * Inputs of cell P: the 3^dim neighbourhood (replicate padding at the mesh
+ * edge) of (T_n - mu_T)/s_T, (T_{n-1} - mu_T)/s_T, (E_n - mu_E)/s_E, ordered
+ * [channel][dz][dy][dx]; output y, guess T_{n+1} = T_n + s_D y.
+ * These calls need options.warm_start != BTE_WARM_NONE. */
+int bte_nn_param_count(bte_ctx* ctx, size_t* n);
+int bte_nn_params(bte_ctx* ctx, float* out, size_t n);
+/* Replaces the parameters (and normalisation) and marks the network trained. */
+int bte_nn_set_params(bte_ctx* ctx, const float* in, size_t n);
+/* The network's guess of T_{n+1} (host, [N_c]) from the current state, before
+ * any plausibility check. */
+int bte_nn_predict(bte_ctx* ctx, double* T_guess, size_t n_cells);
+/* Mean squared error of the current network (normalised units) and its
+ * gradient with respect to the parameter vector, over every cell of one
+ * sample (T_n, T_{n-1}, E_n -> T_{n+1}) given on the host; needs
+ * N_c <= 8192.  y_out (nullable, [N_c]) receives the network outputs.  The
+ * parameters are not changed. */
+int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const double* E_n,
+                    const double* T_next, size_t n_cells, float* grad, size_t n, double* loss,
+                    float* y_out);
 
 /* Releases host-side resources (not the caller's workspace). */
 int bte_destroy(bte_ctx* ctx);

@@ -28,10 +28,13 @@ BTE_WALL_ISOTHERMAL, BTE_WALL_SPECULAR, BTE_WALL_SYMMETRY = 0, 1, 2
 BTE_IMPLICIT_JACOBI, BTE_EXPLICIT_EULER = 0, 1
 BTE_FP64, BTE_FP32_MIXED = 0, 1
 BTE_T_TAU_WEIGHTED, BTE_T_ENERGY = 0, 1
+BTE_WARM_NONE, BTE_WARM_T, BTE_WARM_T_SHIFT = 0, 1, 2
 
 # every symbol include/bte.h declares
 EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "bte_intensity",
-           "bte_energy", "bte_set_state", "bte_sweep_time", "bte_destroy", "bte_last_error")
+           "bte_energy", "bte_set_state", "bte_sweep_time", "bte_nn_param_count", "bte_nn_params",
+           "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_destroy",
+           "bte_last_error")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
@@ -58,12 +61,15 @@ class bte_options(C.Structure):
     _fields_ = [("dt", C.c_double), ("tol", C.c_double), ("max_inner", C.c_int),
                 ("scheme", C.c_int), ("precision", C.c_int), ("t_definition", C.c_int),
                 ("fail_on_notconv", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("warm_start", C.c_int), ("nn_train_steps", C.c_int), ("nn_epochs", C.c_int),
+                ("nn_lr", C.c_float), ("nn_seed", C.c_ulonglong)]
 
 
 class bte_step_stats(C.Structure):
     _fields_ = [("inner", C.c_int), ("converged", C.c_int), ("newton_max", C.c_int),
-                ("reserved", C.c_int), ("res", C.c_double)]
+                ("warm", C.c_int), ("res", C.c_double), ("fallbacks", C.c_int),
+                ("trained", C.c_int), ("nn_loss", C.c_double)]
 
 
 class BteError(RuntimeError):
@@ -100,6 +106,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.bte_energy.argtypes = [C.c_void_p, _dp, C.c_size_t]
     lib.bte_set_state.argtypes = [C.c_void_p, _dp, C.c_size_t, _dp, C.c_size_t]
     lib.bte_sweep_time.argtypes = [C.c_void_p, _dp, _ip]
+    _fp = C.POINTER(C.c_float)
+    lib.bte_nn_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    lib.bte_nn_params.argtypes = [C.c_void_p, _fp, C.c_size_t]
+    lib.bte_nn_set_params.argtypes = [C.c_void_p, _fp, C.c_size_t]
+    lib.bte_nn_predict.argtypes = [C.c_void_p, _dp, C.c_size_t]
+    lib.bte_nn_gradient.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_size_t, _fp, C.c_size_t,
+                                    _dp, _fp]
     lib.bte_destroy.argtypes = [C.c_void_p]
     lib.bte_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -149,6 +162,11 @@ class _Inputs:
         o.t_definition = int(opts["t_definition"])
         o.fail_on_notconv = int(opts.get("fail_on_notconv", 0))
         o.timing = int(bool(opts.get("timing", False)))
+        o.warm_start = int(opts.get("warm_start", 0))
+        o.nn_train_steps = int(opts.get("nn_train_steps", 0))
+        o.nn_epochs = int(opts.get("nn_epochs", 0))
+        o.nn_lr = float(opts.get("nn_lr", 0.0))
+        o.nn_seed = int(opts.get("nn_seed", 0))
         self.mesh, self.dirs, self.bands, self.disp, self.opt = m, d, b, disp, o
 
 
@@ -209,7 +227,8 @@ class Solver:
                 raise ValueError("fixed_inner needs one entry per step")
             fx = (C.c_int * nsteps)(*[int(v) for v in fixed_inner])
         _check(self.lib.bte_step(self._ctx, int(nsteps), fx, st))
-        return [dict(inner=s.inner, converged=s.converged, newton_max=s.newton_max, res=s.res)
+        return [dict(inner=s.inner, converged=s.converged, newton_max=s.newton_max, res=s.res,
+                     warm=s.warm, fallbacks=s.fallbacks, trained=s.trained, nn_loss=s.nn_loss)
                 for s in st[:nsteps]]
 
     def temperature(self) -> np.ndarray:
@@ -233,6 +252,40 @@ class Solver:
         T = _f64(T).reshape(-1)
         _check(self.lib.bte_set_state(self._ctx, I.ctypes.data_as(_dp), I.size,
                                       T.ctypes.data_as(_dp), T.size))
+
+    # ---- learned warm start
+    def nn_param_count(self) -> int:
+        n = C.c_size_t(0)
+        _check(self.lib.bte_nn_param_count(self._ctx, C.byref(n)))
+        return int(n.value)
+
+    def nn_params(self) -> np.ndarray:
+        out = np.empty(self.nn_param_count(), dtype=np.float32)
+        _check(self.lib.bte_nn_params(self._ctx, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                      out.size))
+        return out
+
+    def nn_set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        _check(self.lib.bte_nn_set_params(self._ctx, v.ctypes.data_as(C.POINTER(C.c_float)),
+                                          v.size))
+
+    def nn_predict(self) -> np.ndarray:
+        out = np.empty(self.nc)
+        _check(self.lib.bte_nn_predict(self._ctx, out.ctypes.data_as(_dp), self.nc))
+        return out
+
+    def nn_gradient(self, T_n, T_prev, E_n, T_next):
+        """(loss, gradient, outputs y) of the current network on one given sample."""
+        arrs = [_f64(a).reshape(-1) for a in (T_n, T_prev, E_n, T_next)]
+        g = np.empty(self.nn_param_count(), dtype=np.float32)
+        y = np.empty(self.nc, dtype=np.float32)
+        loss = C.c_double(0.0)
+        fp = C.POINTER(C.c_float)
+        _check(self.lib.bte_nn_gradient(self._ctx, *[a.ctypes.data_as(_dp) for a in arrs],
+                                        self.nc, g.ctypes.data_as(fp), g.size, C.byref(loss),
+                                        y.ctypes.data_as(fp)))
+        return loss.value, g, y
 
     def sweep_time(self):
         """(total ms, count) of sweep kernels timed since the last call."""

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbte.so")
-SOURCES = ["bte_api.hip", "bte_kernels.hip"]
+SOURCES = ["bte_api.hip", "bte_kernels.hip", "bte_nn.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -17,6 +17,7 @@
 
 #include "../../include/bte.h"
 #include "bte_internal.h"
+#include "bte_nn.h"
 
 using namespace bte;
 
@@ -44,6 +45,9 @@ struct Layout {
   size_t ctl, coef, dflags, mirror, w, Cb, xfac, inv_tau, fweight, Iref;
   size_t wallT[6], wallI0[6];
   size_t T, Tprev, E, I0, S, part;
+  // learned warm start (present if warm_start != 0)
+  size_t nn_params, nn_grad, nn_m, nn_v, nn_W1b, nn_W2b, nn_W2Tb, nn_y, nn_hist, nn_loss,
+      nn_fallbacks, nn_XT, nn_H1T, nn_dZ1T, nn_dZ2T, nn_part, nn_shift, nn_guess;
   size_t In, Ia, Ib;
   size_t total;
 };
@@ -54,6 +58,8 @@ struct Shape {
   bool iso[6];
   size_t real_size;
   SweepPlan plan;
+  int warm;       // bte_warm
+  int nn_rec;     // recorded steps before training
 };
 
 int env_int(const char* name, int dflt) {
@@ -89,6 +95,29 @@ Layout make_layout(const Shape& s) {
   L.I0 = take(sizeof(double) * (size_t)s.nb * s.ncp);
   L.S = take(sizeof(double) * (size_t)s.plan.ndg * s.nb * s.ncp);
   L.part = take(sizeof(double) * 2 * (size_t)s.plan.nparts);
+  if (s.warm) {
+    const NnLayout N = make_nn_layout(s.dim);
+    const size_t P = (size_t)N.total;
+    L.nn_params = take(sizeof(float) * P);
+    L.nn_grad = take(sizeof(float) * P);
+    L.nn_m = take(sizeof(float) * P);
+    L.nn_v = take(sizeof(float) * P);
+    L.nn_W1b = take(2 * (size_t)kNnHidden * N.KP);
+    L.nn_W2b = take(2 * (size_t)kNnHidden * kNnHidden);
+    L.nn_W2Tb = take(2 * (size_t)kNnHidden * kNnHidden);
+    L.nn_y = take(sizeof(float) * (size_t)s.nc);
+    // one extra slot for bte_nn_gradient's sample
+    L.nn_hist = take(sizeof(float) * 4 * (size_t)(s.nn_rec + 1) * s.nc);
+    L.nn_loss = take(sizeof(float));
+    L.nn_fallbacks = take(sizeof(int));
+    L.nn_XT = take(2 * (size_t)N.KP * kNnBatch);
+    L.nn_H1T = take(2 * (size_t)kNnHidden * kNnBatch);
+    L.nn_dZ1T = take(2 * (size_t)kNnHidden * kNnBatch);
+    L.nn_dZ2T = take(2 * (size_t)kNnHidden * kNnBatch);
+    L.nn_part = take(sizeof(float) * (size_t)(kNnBatch / 64) * kNnPartWidth);
+    L.nn_shift = take(sizeof(double) * (size_t)s.nb * s.ncp);
+    L.nn_guess = take(sizeof(double) * (size_t)s.nc);
+  }
   const size_t field = s.real_size * (size_t)s.nb * s.nd * s.ncp;
   L.In = take(field);
   L.Ia = take(field);
@@ -120,6 +149,10 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   if (o->t_definition != BTE_T_TAU_WEIGHTED && o->t_definition != BTE_T_ENERGY)
     return fail(BTE_E_INVAL, "unknown temperature definition %d", o->t_definition);
   if (!m->T_init) return fail(BTE_E_INVAL, "T_init is required");
+  if (o->warm_start < BTE_WARM_NONE || o->warm_start > BTE_WARM_T_SHIFT)
+    return fail(BTE_E_INVAL, "unknown warm_start %d", o->warm_start);
+  if (o->warm_start != BTE_WARM_NONE && o->scheme != BTE_IMPLICIT_JACOBI)
+    return fail(BTE_E_INVAL, "the learned warm start seeds the implicit inner iteration only");
   Shape s{};
   s.dim = m->dim;
   s.nx = m->n[0];
@@ -135,6 +168,8 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", 0),
                            env_int("BTE_SWEEP_NDG", 0), env_int("BTE_SWEEP_KIND", -1));
   s.real_size = o->precision == BTE_FP64 ? sizeof(double) : sizeof(float);
+  s.warm = o->warm_start;
+  s.nn_rec = o->nn_train_steps > 0 ? o->nn_train_steps : 20;
   const int nfaces[3] = {s.ny * s.nz, s.nx * s.nz, s.nx * s.ny};
   for (int f = 0; f < 6; ++f) {
     s.nf[f] = nfaces[f / 2];
@@ -177,7 +212,16 @@ struct bte_ctx {
   double* I0;
   double* S;
   double* part;
+  const double* first_shift;  // shift of the first sweep of the current step (or null)
   std::vector<double> Iref;  // host copy of the storage reference per band
+  // learned warm start
+  NnLayout nnL;
+  NnBuffers nnB;
+  double* nn_shift;
+  double* nn_guess;
+  int nn_nrec;      // steps recorded so far
+  int nn_ready;     // network trained (or parameters set)
+  int nn_adam_t;    // Adam steps taken
   bool poisoned;
 };
 
@@ -217,10 +261,11 @@ void find_mirrors(const bte_dirs* d, int dim, std::vector<int>& mirror) {
 }
 
 template <typename Real>
-int enqueue_sweep(bte_ctx* ctx, const void* src, void* dst) {
+int enqueue_sweep(bte_ctx* ctx, const void* src, void* dst, const double* shift) {
   HIP_TRY(launch_sweep<Real>(ctx->stream, ctx->g, ctx->t, ctx->s.plan, 1.0 / ctx->opt.dt,
                              static_cast<const Real*>(src), static_cast<const Real*>(ctx->In),
-                             static_cast<Real*>(dst), ctx->I0, ctx->S, ctx->part, ctx->ctl));
+                             static_cast<Real*>(dst), ctx->I0, ctx->S, ctx->part, ctx->ctl,
+                             shift));
   return BTE_OK;
 }
 
@@ -238,8 +283,9 @@ int enqueue_iteration(bte_ctx* ctx, int j, int fixed_k) {
     }
     HIP_TRY(hipEventRecord(ctx->t_start[j], ctx->stream));
   }
-  int rc = ctx->opt.precision == BTE_FP64 ? enqueue_sweep<double>(ctx, src, dst)
-                                          : enqueue_sweep<float>(ctx, src, dst);
+  const double* shift = (j == 0) ? ctx->first_shift : nullptr;
+  int rc = ctx->opt.precision == BTE_FP64 ? enqueue_sweep<double>(ctx, src, dst, shift)
+                                          : enqueue_sweep<float>(ctx, src, dst, shift);
   if (rc != BTE_OK) return rc;
   if (timing) HIP_TRY(hipEventRecord(ctx->t_stop[j], ctx->stream));
   HIP_TRY(launch_temperature(ctx->stream, ctx->g, ctx->t, ctx->S, ctx->T, ctx->I0, ctx->E,
@@ -250,12 +296,70 @@ int enqueue_iteration(bte_ctx* ctx, int j, int fixed_k) {
   return BTE_OK;
 }
 
+long long gcd_ll(long long a, long long b) {
+  while (b) {
+    const long long t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Trains the network on the recorded steps: normalisation constants, then
+// Adam over minibatches in a pseudo-random sample order (affine permutation
+// i -> (a i + c) mod N with gcd(a, N) = 1), at least two passes and 300 updates
+// unless nn_epochs is given.
+int nn_train(bte_ctx* ctx, double* last_loss) {
+  const int nc = ctx->s.nc;
+  const long long N = (long long)ctx->nn_nrec * nc;
+  HIP_TRY(nn_stats(ctx->stream, ctx->nnL, ctx->nnB, ctx->nn_nrec, nc));
+  long long a = (long long)(0.6180339887 * (double)N) | 1;
+  while (gcd_ll(a, N) != 1) a += 2;
+  const long long per_epoch = (N + kNnBatch - 1) / kNnBatch;
+  int epochs = ctx->opt.nn_epochs;
+  if (epochs <= 0) epochs = (int)std::max<long long>(2, (300 + per_epoch - 1) / per_epoch);
+  const float lr = ctx->opt.nn_lr > 0.f ? ctx->opt.nn_lr : 1e-3f;
+  int batch = 1;
+  for (int e = 0; e < epochs; ++e) {
+    const long long c = ((long long)e * 7919) % N;
+    for (long long b0 = 0; b0 < N; b0 += kNnBatch) {
+      batch = (int)std::min<long long>(kNnBatch, N - b0);
+      ctx->nn_adam_t += 1;
+      HIP_TRY(nn_train_batch(ctx->stream, ctx->g, ctx->nnL, ctx->nnB, N, a, c, b0, batch, lr,
+                             ctx->nn_adam_t, true));
+    }
+  }
+  float loss = 0.f;
+  HIP_TRY(hipMemcpyAsync(&loss, ctx->nnB.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (last_loss) *last_loss = (double)loss / (double)batch;  // mean over the last minibatch
+  ctx->nn_ready = 1;
+  return BTE_OK;
+}
+
 int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
   const bool explicit_mode = ctx->opt.scheme == BTE_EXPLICIT_EULER;
   const int limit = explicit_mode ? 1 : (fixed > 0 ? fixed : ctx->opt.max_inner);
   const bool check = !explicit_mode && fixed <= 0;
-  HIP_TRY(hipMemcpyAsync(ctx->Tprev, ctx->T, sizeof(double) * ctx->s.nc, hipMemcpyDeviceToDevice,
-                         ctx->stream));
+  const int nc = ctx->s.nc;
+  const bool warm = ctx->s.warm && ctx->nn_ready;
+  const bool record = ctx->s.warm && !ctx->nn_ready && ctx->nn_nrec < ctx->s.nn_rec;
+  int fallbacks = 0;
+  float* slot = ctx->nnB.hist + (size_t)ctx->nn_nrec * 4 * nc;
+  if (record) HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, slot, 0));
+  double* shift = nullptr;
+  if (warm) {
+    // guess T_{n+1} from (T_n, T_{n-1}, E_n); apply_guess also moves T_n into T_prev
+    HIP_TRY(hipMemsetAsync(ctx->nnB.fallbacks, 0, sizeof(int), ctx->stream));
+    HIP_TRY(nn_predict(ctx->stream, ctx->g, ctx->nnL, ctx->nnB, ctx->T, ctx->Tprev, ctx->E));
+    shift = ctx->s.warm == BTE_WARM_T_SHIFT ? ctx->nn_shift : nullptr;
+    HIP_TRY(nn_apply_guess(ctx->stream, ctx->g, ctx->t, ctx->nnL, ctx->nnB, ctx->Tprev, ctx->T,
+                           ctx->I0, shift, 10.0f));
+  } else {
+    HIP_TRY(hipMemcpyAsync(ctx->Tprev, ctx->T, sizeof(double) * nc, hipMemcpyDeviceToDevice,
+                           ctx->stream));
+  }
+  ctx->first_shift = shift;
   HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
   for (int j = 0; j < limit; ++j) {
     int rc = enqueue_iteration(ctx, j, check ? 0 : fixed);
@@ -296,12 +400,31 @@ int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
   // the newest iterate becomes I^{n+1}
   void*& last = ((fin.k - 1) & 1) ? ctx->Ib : ctx->Ia;
   std::swap(ctx->In, last);
+  int trained = 0;
+  double loss = 0.0;
+  if (warm) {
+    HIP_TRY(hipMemcpyAsync(&fallbacks, ctx->nnB.fallbacks, sizeof(int), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  if (record) {
+    HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, slot, 1));
+    ctx->nn_nrec += 1;
+    if (ctx->nn_nrec == ctx->s.nn_rec) {
+      int rc = nn_train(ctx, &loss);
+      if (rc != BTE_OK) return rc;
+      trained = 1;
+    }
+  }
   if (st) {
     st->inner = fin.k;
     st->newton_max = fin.newton_max;
     st->res = fin.res;
     st->converged = explicit_mode || (fixed > 0 ? fin.k >= fixed : fin.res <= ctx->opt.tol);
-    st->reserved = 0;
+    st->warm = warm ? 1 : 0;
+    st->fallbacks = fallbacks;
+    st->trained = trained;
+    st->nn_loss = loss;
   }
   if (!explicit_mode && fixed <= 0 && fin.res > ctx->opt.tol && ctx->opt.fail_on_notconv)
     return fail(BTE_E_NOTCONV, "inner iteration hit max_inner=%d with res=%g > tol=%g",
@@ -426,6 +549,33 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   ctx->Ib = ws + L.Ib;
   ctx->timing_ms = 0.0;
   ctx->timing_count = 0;
+  ctx->first_shift = nullptr;
+  ctx->nn_shift = nullptr;
+  ctx->nn_guess = nullptr;
+  ctx->nn_nrec = 0;
+  ctx->nn_ready = 0;
+  ctx->nn_adam_t = 0;
+  ctx->nnB = NnBuffers{};
+  if (s.warm) {
+    ctx->nnL = make_nn_layout(s.dim);
+    NnBuffers& B = ctx->nnB;
+    B.params = at<float>(ws, L.nn_params);
+    B.grad = at<float>(ws, L.nn_grad);
+    B.adam_m = at<float>(ws, L.nn_m);
+    B.adam_v = at<float>(ws, L.nn_v);
+    B.W1b = at<unsigned short>(ws, L.nn_W1b);
+    B.W2b = at<unsigned short>(ws, L.nn_W2b);
+    B.W2Tb = at<unsigned short>(ws, L.nn_W2Tb);
+    B.y = at<float>(ws, L.nn_y);
+    B.hist = at<float>(ws, L.nn_hist);
+    B.loss = at<float>(ws, L.nn_loss);
+    B.fallbacks = at<int>(ws, L.nn_fallbacks);
+    B.scr = NnScratch{at<unsigned short>(ws, L.nn_XT), at<unsigned short>(ws, L.nn_H1T),
+                      at<unsigned short>(ws, L.nn_dZ1T), at<unsigned short>(ws, L.nn_dZ2T),
+                      at<float>(ws, L.nn_part), kNnBatch};
+    ctx->nn_shift = at<double>(ws, L.nn_shift);
+    ctx->nn_guess = at<double>(ws, L.nn_guess);
+  }
 
   Geometry& g = ctx->g;
   g.dim = s.dim;
@@ -512,6 +662,11 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
     CREATE_TRY(launch_broadcast<float>(ctx->stream, g, t, ctx->I0, static_cast<float*>(ctx->In)));
     CREATE_TRY(launch_broadcast<float>(ctx->stream, g, t, ctx->I0, static_cast<float*>(ctx->Ia)));
     CREATE_TRY(launch_broadcast<float>(ctx->stream, g, t, ctx->I0, static_cast<float*>(ctx->Ib)));
+  }
+  if (s.warm) {
+    CREATE_TRY(nn_init(ctx->stream, ctx->nnL, ctx->nnB, opt->nn_seed));
+    CREATE_TRY(hipMemsetAsync(ctx->nnB.fallbacks, 0, sizeof(int), ctx->stream));
+    CREATE_TRY(hipMemsetAsync(ctx->nnB.loss, 0, sizeof(float), ctx->stream));
   }
   CREATE_TRY(hipStreamSynchronize(ctx->stream));
 #undef CREATE_TRY
@@ -617,6 +772,96 @@ int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size
                          ctx->stream));
   HIP_TRY(launch_equilibrium(ctx->stream, ctx->g, ctx->t, ctx->T, ctx->I0, nullptr));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BTE_OK;
+}
+
+static int nn_check(bte_ctx* ctx) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
+  if (!ctx->s.warm) return fail(BTE_E_INVAL, "the context was created without a warm start");
+  return BTE_OK;
+}
+
+int bte_nn_param_count(bte_ctx* ctx, size_t* n) {
+  int rc = nn_check(ctx);
+  if (rc != BTE_OK) return rc;
+  if (!n) return fail(BTE_E_INVAL, "null output");
+  *n = (size_t)ctx->nnL.total;
+  return BTE_OK;
+}
+
+int bte_nn_params(bte_ctx* ctx, float* out, size_t n) {
+  int rc = nn_check(ctx);
+  if (rc != BTE_OK) return rc;
+  if (!out || n != (size_t)ctx->nnL.total)
+    return fail(BTE_E_INVAL, "expected %d parameters", ctx->nnL.total);
+  HIP_TRY(hipMemcpyAsync(out, ctx->nnB.params, sizeof(float) * n, hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BTE_OK;
+}
+
+int bte_nn_set_params(bte_ctx* ctx, const float* in, size_t n) {
+  int rc = nn_check(ctx);
+  if (rc != BTE_OK) return rc;
+  if (!in || n != (size_t)ctx->nnL.total)
+    return fail(BTE_E_INVAL, "expected %d parameters", ctx->nnL.total);
+  const float* nm = in + ctx->nnL.o_norm;
+  if (!(nm[1] > 0.f) || !(nm[3] > 0.f) || !(nm[4] > 0.f))
+    return fail(BTE_E_INVAL, "normalisation scales s_T, s_E, s_D must be positive");
+  HIP_TRY(hipMemcpyAsync(ctx->nnB.params, in, sizeof(float) * n, hipMemcpyHostToDevice,
+                         ctx->stream));
+  HIP_TRY(nn_refresh(ctx->stream, ctx->nnL, ctx->nnB));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->nn_ready = 1;
+  return BTE_OK;
+}
+
+int bte_nn_predict(bte_ctx* ctx, double* T_guess, size_t n_cells) {
+  int rc = nn_check(ctx);
+  if (rc != BTE_OK) return rc;
+  if (!T_guess || n_cells != (size_t)ctx->s.nc)
+    return fail(BTE_E_INVAL, "expected %d cells", ctx->s.nc);
+  HIP_TRY(nn_predict(ctx->stream, ctx->g, ctx->nnL, ctx->nnB, ctx->T, ctx->Tprev, ctx->E));
+  HIP_TRY(nn_guess_out(ctx->stream, ctx->s.nc, ctx->nnL, ctx->nnB, ctx->T, ctx->nn_guess));
+  HIP_TRY(hipMemcpyAsync(T_guess, ctx->nn_guess, sizeof(double) * n_cells, hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BTE_OK;
+}
+
+int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const double* E_n,
+                    const double* T_next, size_t n_cells, float* grad, size_t n, double* loss,
+                    float* y_out) {
+  int rc = nn_check(ctx);
+  if (rc != BTE_OK) return rc;
+  const int nc = ctx->s.nc;
+  if (!T_n || !T_prev || !E_n || !T_next || !grad || n_cells != (size_t)nc ||
+      n != (size_t)ctx->nnL.total)
+    return fail(BTE_E_INVAL, "bad arguments (expected %d cells, %d parameters)", nc,
+                ctx->nnL.total);
+  if (nc > kNnBatch) return fail(BTE_E_INVAL, "at most %d cells", kNnBatch);
+  std::vector<float> sample(4 * (size_t)nc);
+  for (int P = 0; P < nc; ++P) {
+    sample[P] = (float)T_n[P];
+    sample[(size_t)nc + P] = (float)T_prev[P];
+    sample[2 * (size_t)nc + P] = (float)E_n[P];
+    sample[3 * (size_t)nc + P] = (float)T_next[P];
+  }
+  // the extra history slot after the recording slots
+  NnBuffers B = ctx->nnB;
+  B.hist = ctx->nnB.hist + (size_t)ctx->s.nn_rec * 4 * nc;
+  HIP_TRY(hipMemcpyAsync(B.hist, sample.data(), sizeof(float) * sample.size(),
+                         hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(nn_train_batch(ctx->stream, ctx->g, ctx->nnL, B, nc, 1, 0, 0, nc, 0.f, 1, false,
+                         y_out ? B.y : nullptr));
+  float l = 0.f;
+  if (y_out)
+    HIP_TRY(hipMemcpyAsync(y_out, B.y, sizeof(float) * nc, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(grad, B.grad, sizeof(float) * n, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(&l, B.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (loss) *loss = (double)l / (double)nc;
   return BTE_OK;
 }
 

@@ -92,7 +92,7 @@ template <typename Real>
 hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
                         const SweepPlan& plan, double inv_dt, const Real* Ik, const Real* In,
                         Real* Iout, const double* I0, double* S, double* part,
-                        const Control* ctl);
+                        const Control* ctl, const double* shift);
 
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* S, double* T, double* I0, double* E, Control* ctl);

@@ -82,20 +82,30 @@ struct SweepParams {
   double* __restrict__ part;
   const Control* ctl;
   double inv_dt;
+  // first sweep of a warm-started step: I^(0) = I^n + shift[b][P] (isotropic
+  // equilibrium shift at the guessed temperature); null otherwise
+  const double* __restrict__ shift;
 };
+
+// v + shift[b][P] in the first sweep of a warm-started step, v otherwise.
+template <bool SHIFT, typename Real>
+__device__ __forceinline__ double shifted(double v, const SweepParams<Real>& p, int b, int P) {
+  if constexpr (SHIFT) return v + p.shift[(size_t)b * p.g.ncp + P];
+  else return v;
+}
 
 // Upwind value along one axis for a cell with coordinate `coord` along it:
 // the neighbour on the inflow side, or the wall ghost (Eq. eq-bdry) when the
 // inflow face is a wall face.
-template <typename Real>
+template <bool SHIFT, typename Real>
 __device__ __forceinline__ double upwind_value(const SweepParams<Real>& p, const Real* slab,
                                                const Real* band_base, double iref, int P, int b,
                                                int d, int axis, bool from_minus, int coord,
                                                int n, int stride, int face) {
   if (from_minus) {
-      if (coord > 0) return decode(iref, slab[P - stride]);
+    if (coord > 0) return shifted<SHIFT>(decode(iref, slab[P - stride]), p, b, P - stride);
   } else {
-    if (coord < n - 1) return decode(iref, slab[P + stride]);
+    if (coord < n - 1) return shifted<SHIFT>(decode(iref, slab[P + stride]), p, b, P + stride);
   }
   const int side = 2 * axis + (from_minus ? 0 : 1);
   if (p.t.wall[side] == 0) {  // isothermal: equilibrium at the wall temperature
@@ -103,7 +113,7 @@ __device__ __forceinline__ double upwind_value(const SweepParams<Real>& p, const
   }
   // specular / symmetry: the cell's own intensity in the mirrored direction
   const int r = p.t.mirror[axis * p.g.nd + d];
-  return decode(iref, band_base[(size_t)r * p.g.ncp + P]);
+  return shifted<SHIFT>(decode(iref, band_base[(size_t)r * p.g.ncp + P]), p, b, P);
 }
 
 // One point-Jacobi sweep (or forward-Euler update) over every direction of one
@@ -116,7 +126,7 @@ __device__ __forceinline__ double upwind_value(const SweepParams<Real>& p, const
 //   I^{k+1} = I^k + R * scale,   scale = 1/(1/dt + 1/tau_b + sum_axis c_axis)
 // Forward Euler passes I^k = I^n and scale = dt, which is Eq.
 // eq-conservation-discrete with the same upwind fluxes.
-template <typename Real, int DIM>
+template <typename Real, int DIM, bool SHIFT>
 __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Real> p) {
   if (p.ctl->converged) return;
   const int b = blockIdx.y;
@@ -153,22 +163,22 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Re
     const double wd = p.t.w[d];
     if (active) {
       const Real* slab = Ikb + (size_t)d * ncp;
-      const double ik = decode(iref, slab[P]);
+      const double ik = shifted<SHIFT>(decode(iref, slab[P]), p, b, P);
       const double in = decode(iref, Inb[(size_t)d * ncp + P]);
       double acc = (in - ik) * p.inv_dt + (I0P - ik) * inv_tau;
       if (dir_pos(fl, 0) || dir_neg(fl, 0)) {
         const double up =
-            upwind_value(p, slab, Ikb, iref, P, b, d, 0, dir_pos(fl, 0), x, g.nx, 1, face_x);
+            upwind_value<SHIFT>(p, slab, Ikb, iref, P, b, d, 0, dir_pos(fl, 0), x, g.nx, 1, face_x);
         acc += cf.c[0] * (up - ik);
       }
       if (dir_pos(fl, 1) || dir_neg(fl, 1)) {
         const double up =
-            upwind_value(p, slab, Ikb, iref, P, b, d, 1, dir_pos(fl, 1), y, g.ny, sy, face_y);
+            upwind_value<SHIFT>(p, slab, Ikb, iref, P, b, d, 1, dir_pos(fl, 1), y, g.ny, sy, face_y);
         acc += cf.c[1] * (up - ik);
       }
       if (DIM == 3 && (dir_pos(fl, 2) || dir_neg(fl, 2))) {
         const double up =
-            upwind_value(p, slab, Ikb, iref, P, b, d, 2, dir_pos(fl, 2), z, g.nz, sz, face_z);
+            upwind_value<SHIFT>(p, slab, Ikb, iref, P, b, d, 2, dir_pos(fl, 2), z, g.nz, sz, face_z);
         acc += cf.c[2] * (up - ik);
       }
       const Real inew_r = encode<Real>(iref, ik + acc * cf.scale);
@@ -265,13 +275,13 @@ __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t
 // Ghost intensity on an inflow wall face (Eq. eq-bdry) for cell P of band b,
 // direction d: equilibrium at the wall temperature (isothermal) or the cell's
 // own intensity in the mirrored direction (specular / symmetry).
-template <typename Real>
+template <bool SHIFT, typename Real>
 __device__ __forceinline__ double wall_ghost(const SweepParams<Real>& p, const Real* band_base,
                                              double iref, int side, int axis, int b, int d, int P,
                                              int face) {
   if (p.t.wall[side] == 0) return p.t.wall_I0[side][(size_t)b * p.t.wall_nf[side] + face];
   const int r = p.t.mirror[axis * p.g.nd + d];
-  return decode(iref, band_base[(size_t)r * p.g.ncp + P]);
+  return shifted<SHIFT>(decode(iref, band_base[(size_t)r * p.g.ncp + P]), p, b, P);
 }
 
 // The same update as sweep_kernel for 2D meshes, organised for reuse: a
@@ -282,7 +292,7 @@ __device__ __forceinline__ double wall_ghost(const SweepParams<Real>& p, const R
 // tile edges read halo values (the x halo column is fetched by RY lanes in one
 // load and broadcast with readlane).  The per-(direction group, band, cell)
 // energy partials and per-workgroup norm partials are fused as in sweep_kernel.
-template <typename Real, int RY>
+template <typename Real, int RY, bool SHIFT>
 __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepParams<Real> p,
                                                                    const int ntx, const int dgs) {
   if (p.ctl->converged) return;
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
 #pragma unroll
   for (int j = 0; j < RY; ++j) rowoff[j] = row0 + (j < nrows ? j : 0) * rowb;
 
-  double I0r[RY], S[RY], Sc[RY];
+  double I0r[RY], S[RY], Sc[RY], sh[RY];
   {
     const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
 #pragma unroll
@@ -331,6 +341,13 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
       I0r[j] = __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]);
       S[j] = 0.0;
       Sc[j] = 0.0;
+      sh[j] = 0.0;
+      if constexpr (SHIFT) {
+        const auto r1 = slab_rsrc(p.shift + (size_t)b * ncp, g.nc * 8);
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r1, (colok ? lane : 0) * 8,
+                                                            rowoff[j] / (int)sizeof(Real) * 8, 0);
+        sh[j] = __longlong_as_double(((long long)u[1] << 32) | (unsigned int)u[0]);
+      }
     }
   }
   double num = 0.0, den = 0.0;
@@ -352,6 +369,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
         ik[j] += iref;
         in[j] += iref;
       }
+      if constexpr (SHIFT) ik[j] += sh[j];
     }
     const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
     const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
@@ -359,19 +377,20 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
     double hy = 0.0;
     if (colok && nrows > 0) {
       if (ypos) {
-        hy = (y0 > 0) ? decode(iref, sk[(size_t)(y0 - 1) * nx + x])
-                      : wall_ghost(p, Ikb, iref, 2, 1, b, d, x, x);
+        hy = (y0 > 0) ? shifted<SHIFT>(decode(iref, sk[(size_t)(y0 - 1) * nx + x]), p, b, (y0 - 1) * nx + x)
+                      : wall_ghost<SHIFT>(p, Ikb, iref, 2, 1, b, d, x, x);
       } else if (yneg) {
         const int yh = y0 + nrows;
-        hy = (yh < ny) ? decode(iref, sk[(size_t)yh * nx + x])
-                       : wall_ghost(p, Ikb, iref, 3, 1, b, d, (yh - 1) * nx + x, x);
+        hy = (yh < ny) ? shifted<SHIFT>(decode(iref, sk[(size_t)yh * nx + x]), p, b, yh * nx + x)
+                       : wall_ghost<SHIFT>(p, Ikb, iref, 3, 1, b, d, (yh - 1) * nx + x, x);
       }
     }
     // x halo column on the inflow side of the tile: lane j holds row y0 + j
     double hx = 0.0;
     if (lane < nrows && (xpos || xneg)) {
       const int xh = xpos ? x0 - 1 : x0 + 64;
-      if (xh >= 0 && xh < nx) hx = decode(iref, sk[(size_t)(y0 + lane) * nx + xh]);
+      if (xh >= 0 && xh < nx)
+        hx = shifted<SHIFT>(decode(iref, sk[(size_t)(y0 + lane) * nx + xh]), p, b, (y0 + lane) * nx + xh);
     }
     // lane holding the x-upwind neighbour (direction sign is wave-uniform)
     const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
@@ -385,11 +404,11 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
         const double v = ik[j];
         double acc = (in[j] - v) * p.inv_dt + (I0r[j] - v) * inv_tau;
         if (xpos) {
-          const double up = (x == 0) ? wall_ghost(p, Ikb, iref, 0, 0, b, d, P, y)
+          const double up = (x == 0) ? wall_ghost<SHIFT>(p, Ikb, iref, 0, 0, b, d, P, y)
                                      : (lane == 0 ? hxj : nbr);
           acc += cf.c[0] * (up - v);
         } else if (xneg) {
-          const double up = (x == nx - 1) ? wall_ghost(p, Ikb, iref, 1, 0, b, d, P, y)
+          const double up = (x == nx - 1) ? wall_ghost<SHIFT>(p, Ikb, iref, 1, 0, b, d, P, y)
                                           : (lane == 63 ? hxj : nbr);
           acc += cf.c[0] * (up - v);
         }
@@ -476,45 +495,53 @@ SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int r
   return pl;
 }
 
-template <typename Real>
-hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
-                        const SweepPlan& plan, double inv_dt, const Real* Ik, const Real* In,
-                        Real* Iout, const double* I0, double* S, double* part,
-                        const Control* ctl) {
-  const SweepParams<Real> p{g, t, Ik, In, Iout, I0, S, part, ctl, inv_dt};
+template <typename Real, bool SHIFT>
+static void launch_sweep_t(hipStream_t stream, const SweepPlan& plan, const SweepParams<Real>& p) {
+  const Geometry& g = p.g;
   if (plan.kind == kSweepColumnWalk2D) {
     const dim3 grid(plan.ntiles, g.nb, plan.ndg);
     switch (plan.ry) {
       case 4:
-        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 4>), grid, dim3(kSweepBlock), 0, stream, p,
-                           plan.ntx, plan.dgs);
+        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+                           stream, p, plan.ntx, plan.dgs);
         break;
       case 8:
-        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 8>), grid, dim3(kSweepBlock), 0, stream, p,
-                           plan.ntx, plan.dgs);
+        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 8, SHIFT>), grid, dim3(kSweepBlock), 0,
+                           stream, p, plan.ntx, plan.dgs);
         break;
       default:
-        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 16>), grid, dim3(kSweepBlock), 0, stream,
-                           p, plan.ntx, plan.dgs);
+        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 16, SHIFT>), grid, dim3(kSweepBlock), 0,
+                           stream, p, plan.ntx, plan.dgs);
         break;
     }
-    return hipGetLastError();
+    return;
   }
   const dim3 grid(plan.ntiles, g.nb);
   if (g.dim == 3)
-    hipLaunchKernelGGL((sweep_kernel<Real, 3>), grid, dim3(kSweepBlock), 0, stream, p);
+    hipLaunchKernelGGL((sweep_kernel<Real, 3, SHIFT>), grid, dim3(kSweepBlock), 0, stream, p);
   else
-    hipLaunchKernelGGL((sweep_kernel<Real, 2>), grid, dim3(kSweepBlock), 0, stream, p);
+    hipLaunchKernelGGL((sweep_kernel<Real, 2, SHIFT>), grid, dim3(kSweepBlock), 0, stream, p);
+}
+
+template <typename Real>
+hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
+                        const SweepPlan& plan, double inv_dt, const Real* Ik, const Real* In,
+                        Real* Iout, const double* I0, double* S, double* part,
+                        const Control* ctl, const double* shift) {
+  const SweepParams<Real> p{g, t, Ik, In, Iout, I0, S, part, ctl, inv_dt, shift};
+  if (shift) launch_sweep_t<Real, true>(stream, plan, p);
+  else launch_sweep_t<Real, false>(stream, plan, p);
   return hipGetLastError();
 }
 
 template hipError_t launch_sweep<double>(hipStream_t, const Geometry&, const Tables&,
                                          const SweepPlan&, double, const double*, const double*,
                                          double*, const double*, double*, double*,
-                                         const Control*);
+                                         const Control*, const double*);
 template hipError_t launch_sweep<float>(hipStream_t, const Geometry&, const Tables&,
                                         const SweepPlan&, double, const float*, const float*,
-                                        float*, const double*, double*, double*, const Control*);
+                                        float*, const double*, double*, double*, const Control*,
+                                        const double*);
 
 // ---------------------------------------------------------------- temperature
 // Each cell is handled by kLanesPerCell lanes of one wavefront; lane l of a
