@@ -86,15 +86,132 @@ def copy_probe():
     log(f"copy probe: {4 * n} bytes read, {4 * n} bytes written")
 
 
+def run_solo(bte, inst, prec, steps, label, timing=False, **opts):
+    """Steps one fresh context ``steps`` times; returns wall time, per-step stats,
+    final temperature and (with timing) the sweep-kernel time."""
+    import torch
+    sol = bte.Solver(inst, device="cuda:0", precision=prec, timing=timing, **opts)
+    torch.cuda.synchronize()
+    sol.sweep_time()  # reset accumulators
+    t0 = time.perf_counter()
+    stats, done = [], 0
+    while done < steps:
+        n = min(20, steps - done)
+        stats += sol.step(n)
+        done += n
+        log(f"{label}: steps {done}/{steps}, inner last={stats[-1]['inner']}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms, nsweeps = sol.sweep_time()
+    T = sol.temperature()
+    sol.close()
+    return {"wall": wall, "stats": stats, "T": T, "sweep_ms": sweep_ms, "nsweeps": nsweeps}
+
+
+def max_rel(a, b):
+    import numpy as np
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def run_c5(args):
+    """Batched workload: 64 uneven 2D/3D geometries stepped together (FP32
+    intensities, learned warm start after 20 recorded steps, one persistent
+    sweep per inner iteration, captured as a HIP graph, autotuned 2D layouts),
+    against the same geometries stepped one after another in plain FP64."""
+    import tempfile
+
+    import torch
+    from paper_2305_19400_amd import bte, inputs
+
+    steps = args.steps if args.steps is not None else 30
+    insts = inputs.config_c5(nsteps=steps)
+    total_dof = sum(i.n_dof for i in insts)
+    log(f"c5: {len(insts)} geometries, {total_dof:.3e} DOF, {steps} steps")
+    stream = torch.cuda.Stream()
+    cache = os.path.join(tempfile.gettempdir(), "bte_layouts.txt")
+    sols = []
+    for k, inst in enumerate(insts):
+        s = bte.Solver(inst, stream=stream, precision=bte.BTE_FP32_MIXED,
+                       warm_start=bte.BTE_WARM_T, nn_train_steps=20, nn_seed=inst.seed)
+        if inst.dim == 2:
+            s.autotune(cache, ry=4)
+        sols.append(s)
+        if (k + 1) % 16 == 0:
+            log(f"c5: {k + 1} contexts created")
+    batch = bte.Batch(sols, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_step, done = [], 0
+    while done < steps:
+        n = min(5, steps - done)
+        per_step += batch.step(n)
+        done += n
+        log(f"c5 batch: steps {done}/{steps}")
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    T_b = [s.temperature() for s in sols]
+    batch.close()
+    for s in sols:
+        s.close()
+    del sols
+    inner_b = [sum(st[g]["inner"] for st in per_step) for g in range(len(insts))]
+    updates_b = sum(k * i.n_dof for k, i in zip(inner_b, insts))
+
+    wall_s, inner_s, after_s, err = 0.0, [], 0, 0.0
+    for g, inst in enumerate(insts):
+        r = run_solo(bte, inst, bte.BTE_FP64, steps, f"c5 sequential fp64 {g}")
+        wall_s += r["wall"]
+        inner_s.append(sum(x["inner"] for x in r["stats"]))
+        after_s += sum(x["inner"] for x in r["stats"][20:])
+        err = max(err, max_rel(T_b[g], r["T"]))
+    updates_s = sum(k * i.n_dof for k, i in zip(inner_s, insts))
+    warm = sum(per_step[k][g]["inner"] for k in range(20, steps) for g in range(len(insts)))
+    out = {
+        "metric": "cell-dir-band updates/s (batched uneven geometries)",
+        "value": updates_b / wall_b,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": wall_b / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded geometries, band tables, hot spots, wall mixes)",
+        "config": {"workload": "c5_batch64", "geometries": len(insts), "total_dof": total_dof,
+                   "dims": {"2d": sum(i.dim == 2 for i in insts),
+                            "3d": sum(i.dim == 3 for i in insts)},
+                   "cells": [min(i.n_cells for i in insts), max(i.n_cells for i in insts)],
+                   "time_steps": steps, "warm_start": "T guess, trained after 20 steps",
+                   "launch": "persistent sweep + HIP graph per inner iteration"},
+        "time_to_solution_s": wall_b,
+        "inner_sweeps": sum(inner_b),
+        "sequential_fp64": {"value": updates_s / wall_s, "unit": "updates/s",
+                            "time_to_solution_s": wall_s, "inner_sweeps": sum(inner_s),
+                            "speedup_time_to_solution": wall_s / wall_b,
+                            "T_max_rel_err_batch_vs_fp64": err},
+        "roofline": None,
+        "note": "per-launch timing is off inside batches; the sweep roofline is reported "
+                "by the single-geometry workloads",
+    }
+    if steps > 20:
+        out["inner_sweeps_after_training"] = {"batch_fp32_warm": warm, "sequential_fp64": after_s}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="time steps (default 200; 30 for c5)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
-                    help="c2 (default, the benchmarked 2D case) or the 3D cases")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2 (default, the benchmarked 2D case), the 3D cases, or the batch")
+    ap.add_argument("--no-tts", action="store_true",
+                    help="skip the FP32 + learned warm start time-to-solution comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -105,6 +222,11 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the band-sharded design is described, not built).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c5":
+        run_c5(args)
+        return
+    if args.steps is None:
+        args.steps = 200
 
     import torch
     from paper_2305_19400_amd import bte, inputs
@@ -121,23 +243,9 @@ def main():
             sol.step(args.warmup)
         log(f"warmup: {args.warmup} steps done")
 
-    sol = bte.Solver(inst, device="cuda:0", precision=prec, timing=True)
-    torch.cuda.synchronize(dev)
-    sol.sweep_time()  # reset accumulators
-    t0 = time.perf_counter()
-    stats = []
-    chunk = 20
-    done = 0
-    while done < args.steps:
-        n = min(chunk, args.steps - done)
-        stats += sol.step(n)
-        done += n
-        log(f"steps {done}/{args.steps}, inner last={stats[-1]['inner']}")
-    torch.cuda.synchronize(dev)
-    wall = time.perf_counter() - t0
-    sweep_ms, nsweeps = sol.sweep_time()
-    T = sol.temperature()
-    sol.close()
+    main_run = run_solo(bte, inst, prec, args.steps, "timed", timing=True)
+    wall, stats, T = main_run["wall"], main_run["stats"], main_run["T"]
+    sweep_ms, nsweeps = main_run["sweep_ms"], main_run["nsweeps"]
 
     sweeps = sum(s["inner"] for s in stats)
     updates = sweeps * inst.n_dof
@@ -155,7 +263,8 @@ def main():
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64" if prec == bte.BTE_FP64 else "f32+f64",
-        "data": "synthetic (seeded Si-like band tables, strip heater)",
+        "data": ("synthetic (seeded Si-like band tables, "
+                 + ("strip heater)" if inst.dim == 2 else "Gaussian hot spot)")),
         "config": {"workload": inst.name, "mesh": "x".join(str(v) for v in inst.n[:inst.dim]),
                    "dirs": inst.n_dirs,
                    "bands": inst.n_bands, "dt_s": inst.dt, "tol": inst.tol,
@@ -168,13 +277,34 @@ def main():
         "T_max_K": float(T.max()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel", "avg_ms": avg_sweep_s * 1e3,
+                     "kernel": "sweep2d_walk_kernel" if inst.dim == 2 else "sweep_kernel",
+                     "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
     }
     if prec == bte.BTE_FP64 and args.workload == "c2":
         out["roofline"]["traffic"] = measured_traffic(
             os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
             os.path.join(ROOT, "profiles", "sweep2d_c2_fp64_counters.json"))
+    if prec == bte.BTE_FP64 and not args.no_tts:
+        # Same workload and tolerance in FP32 storage with the learned warm
+        # start (trained on the first 20 steps): time to solution and the
+        # temperature error against this FP64 run.
+        warm = bte.BTE_WARM_T_SHIFT
+        r = run_solo(bte, inst, bte.BTE_FP32_MIXED, args.steps, "fp32+nn", warm_start=warm,
+                     nn_train_steps=20, nn_seed=1)
+        k32 = sum(x["inner"] for x in r["stats"])
+        trained = [x["nn_loss"] for x in r["stats"] if x["trained"]]
+        out["time_to_solution"] = {
+            "fp64_plain_s": wall, "fp32_nn_s": r["wall"], "speedup": wall / r["wall"],
+            "fp64_inner_sweeps": sweeps, "fp32_nn_inner_sweeps": k32,
+            "inner_sweeps_after_training": {
+                "fp64_plain": sum(x["inner"] for x in stats[20:]),
+                "fp32_nn": sum(x["inner"] for x in r["stats"][20:])},
+            "T_max_rel_err_fp32_nn_vs_fp64": max_rel(r["T"], T), "T_rel_target": 1e-4,
+            "nn": {"inputs": "3^dim patch x (T_n, T_n-1, E_n)", "hidden": [128, 128],
+                   "train_steps": 20, "loss": trained[0] if trained else None,
+                   "warm_start": "T guess + intensity shift"},
+            "fallback_cells_per_step_max": max(x["fallbacks"] for x in r["stats"])}
     if not args.no_cpu_baseline and args.workload == "c2":
         out["cpu_baseline"] = cpu_baseline(inst, log)
     print(json.dumps(out), flush=True)

@@ -215,6 +215,32 @@ int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const
                     const double* T_next, size_t n_cells, float* grad, size_t n, double* loss,
                     float* y_out);
 
+/* Sweep layout tuning.  Times the candidate layouts (rows walked per wave,
+ * direction groups) of this context's shape on the device and keeps the
+ * fastest, or takes the layout recorded for the same shape in the text file
+ * cache_path (appended to after a measurement; NULL = no cache).  *ry is
+ * in/out: 4 or 8 on entry restricts the search to that row count (batches
+ * need 4), anything else searches all.  The choice is returned in *ry, *ndg
+ * and its sweep time (measured now or recorded in the cache) in *sweep_ms (all
+ * nullable; -1 for shapes with a single layout: 3D contexts have one). */
+int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry, int* ndg, double* sweep_ms);
+
+/* Batched stepping of independent contexts (geometries of any size, 2D or
+ * 3D, one precision, sharing one stream): every inner iteration of all of them
+ * runs as one persistent sweep over a work list of (geometry, tile, band,
+ * direction group) items -- largest geometry first, converged geometries
+ * skipped -- followed by batched temperature and convergence kernels.  With
+ * use_graph (and a non-null stream) that iteration is captured once as a HIP
+ * graph and replayed until every geometry has converged.  Each context gives
+ * exactly the results it gives when stepped alone.  Batches need the 4-row
+ * sweep layout, the implicit scheme, and warm start NONE or T.  The batch
+ * holds small device arrays of its own (descriptors, work list). */
+typedef struct bte_batch bte_batch;
+int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out);
+/* stats (nullable): [nsteps][n] */
+int bte_batch_step(bte_batch* batch, int nsteps, bte_step_stats* stats);
+int bte_batch_destroy(bte_batch* batch);
+
 /* Releases host-side resources (not the caller's workspace). */
 int bte_destroy(bte_ctx* ctx);
 

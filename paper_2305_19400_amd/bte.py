@@ -33,7 +33,8 @@ BTE_WARM_NONE, BTE_WARM_T, BTE_WARM_T_SHIFT = 0, 1, 2
 # every symbol include/bte.h declares
 EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "bte_intensity",
            "bte_energy", "bte_set_state", "bte_sweep_time", "bte_nn_param_count", "bte_nn_params",
-           "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_destroy",
+           "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_autotune",
+           "bte_batch_create", "bte_batch_step", "bte_batch_destroy", "bte_destroy",
            "bte_last_error")
 
 _dp = C.POINTER(C.c_double)
@@ -114,6 +115,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.bte_nn_gradient.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_size_t, _fp, C.c_size_t,
                                     _dp, _fp]
     lib.bte_destroy.argtypes = [C.c_void_p]
+    lib.bte_autotune.argtypes = [C.c_void_p, C.c_char_p, _ip, _ip, _dp]
+    lib.bte_batch_create.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int,
+                                     C.POINTER(C.c_void_p)]
+    lib.bte_batch_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(bte_step_stats)]
+    lib.bte_batch_destroy.argtypes = [C.c_void_p]
     lib.bte_last_error.restype = C.c_char_p
     for name in EXPORTS:
         getattr(lib, name).restype = C.c_char_p if name == "bte_last_error" else C.c_int
@@ -287,6 +293,14 @@ class Solver:
                                         y.ctypes.data_as(fp)))
         return loss.value, g, y
 
+    def autotune(self, cache_path: Optional[str] = None, ry: int = 0):
+        """Pick the fastest sweep layout for this shape (only layouts walking ``ry``
+        rows per wave if ry is 4 or 8); returns (ry, ndg, sweep ms)."""
+        ry, ndg, ms = C.c_int(int(ry)), C.c_int(0), C.c_double(0.0)
+        _check(self.lib.bte_autotune(self._ctx, cache_path.encode() if cache_path else None,
+                                     C.byref(ry), C.byref(ndg), C.byref(ms)))
+        return ry.value, ndg.value, ms.value
+
     def sweep_time(self):
         """(total ms, count) of sweep kernels timed since the last call."""
         ms = C.c_double(0.0)
@@ -298,6 +312,48 @@ class Solver:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self.lib.bte_destroy(self._ctx)
             self._ctx = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _stats_dict(s) -> dict:
+    return dict(inner=s.inner, converged=s.converged, newton_max=s.newton_max, res=s.res,
+                warm=s.warm, fallbacks=s.fallbacks, trained=s.trained, nn_loss=s.nn_loss)
+
+
+class Batch:
+    """Steps several Solvers (sharing one stream) together: persistent sweep over
+    all geometries, captured as a HIP graph per inner iteration."""
+
+    def __init__(self, solvers, use_graph: bool = True):
+        self.lib = load_library()
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        arr = (C.c_void_p * n)(*[s._ctx.value for s in self.solvers])
+        self._b = C.c_void_p(0)
+        _check(self.lib.bte_batch_create(n, arr, int(bool(use_graph)), C.byref(self._b)))
+
+    def step(self, nsteps: int = 1):
+        """Returns stats[step][geometry]."""
+        n = len(self.solvers)
+        st = (bte_step_stats * max(1, nsteps * n))()
+        _check(self.lib.bte_batch_step(self._b, int(nsteps), st))
+        return [[_stats_dict(st[k * n + i]) for i in range(n)] for k in range(nsteps)]
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self.lib.bte_batch_destroy(self._b)
+            self._b = C.c_void_p(0)
 
     def __del__(self):
         try:

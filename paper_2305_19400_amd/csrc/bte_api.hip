@@ -58,6 +58,7 @@ struct Shape {
   bool iso[6];
   size_t real_size;
   SweepPlan plan;
+  int ndg_cap, nparts_cap;  // room for any layout the autotuner may pick
   int warm;       // bte_warm
   int nn_rec;     // recorded steps before training
 };
@@ -93,8 +94,8 @@ Layout make_layout(const Shape& s) {
   L.Tprev = take(sizeof(double) * (size_t)s.ncp);
   L.E = take(sizeof(double) * (size_t)s.ncp);
   L.I0 = take(sizeof(double) * (size_t)s.nb * s.ncp);
-  L.S = take(sizeof(double) * (size_t)s.plan.ndg * s.nb * s.ncp);
-  L.part = take(sizeof(double) * 2 * (size_t)s.plan.nparts);
+  L.S = take(sizeof(double) * (size_t)s.ndg_cap * s.nb * s.ncp);
+  L.part = take(sizeof(double) * 2 * (size_t)s.nparts_cap);
   if (s.warm) {
     const NnLayout N = make_nn_layout(s.dim);
     const size_t P = (size_t)N.total;
@@ -167,6 +168,15 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   // family (tuning knobs).
   s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", 0),
                            env_int("BTE_SWEEP_NDG", 0), env_int("BTE_SWEEP_KIND", -1));
+  s.ndg_cap = s.plan.ndg;
+  s.nparts_cap = s.plan.nparts;
+  if (s.plan.kind == kSweepColumnWalk2D) {
+    // the 4-row layout has the most tiles; up to 16 direction groups
+    const SweepPlan widest = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 4,
+                                             std::min(s.nd, 16), kSweepColumnWalk2D);
+    s.ndg_cap = std::max(s.ndg_cap, widest.ndg);
+    s.nparts_cap = std::max(s.nparts_cap, widest.ntiles * s.nb * s.ndg_cap);
+  }
   s.real_size = o->precision == BTE_FP64 ? sizeof(double) : sizeof(float);
   s.warm = o->warm_start;
   s.nn_rec = o->nn_train_steps > 0 ? o->nn_train_steps : 20;
@@ -337,19 +347,28 @@ int nn_train(bte_ctx* ctx, double* last_loss) {
   return BTE_OK;
 }
 
-int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
-  const bool explicit_mode = ctx->opt.scheme == BTE_EXPLICIT_EULER;
-  const int limit = explicit_mode ? 1 : (fixed > 0 ? fixed : ctx->opt.max_inner);
-  const bool check = !explicit_mode && fixed <= 0;
+// What one time step decided before its inner loop.
+struct StepState {
+  bool explicit_mode, check, warm, record;
+  int fixed, limit;
+  float* slot;
+};
+
+// Everything before the inner loop: record the network's training inputs,
+// or apply its guess of T_{n+1} (which also moves T_n into T_prev); otherwise
+// T_prev <- T_n.
+int step_begin(bte_ctx* ctx, int fixed, StepState* ss) {
   const int nc = ctx->s.nc;
-  const bool warm = ctx->s.warm && ctx->nn_ready;
-  const bool record = ctx->s.warm && !ctx->nn_ready && ctx->nn_nrec < ctx->s.nn_rec;
-  int fallbacks = 0;
-  float* slot = ctx->nnB.hist + (size_t)ctx->nn_nrec * 4 * nc;
-  if (record) HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, slot, 0));
+  ss->explicit_mode = ctx->opt.scheme == BTE_EXPLICIT_EULER;
+  ss->fixed = fixed;
+  ss->limit = ss->explicit_mode ? 1 : (fixed > 0 ? fixed : ctx->opt.max_inner);
+  ss->check = !ss->explicit_mode && fixed <= 0;
+  ss->warm = ctx->s.warm && ctx->nn_ready;
+  ss->record = ctx->s.warm && !ctx->nn_ready && ctx->nn_nrec < ctx->s.nn_rec;
+  ss->slot = ctx->s.warm ? ctx->nnB.hist + (size_t)ctx->nn_nrec * 4 * nc : nullptr;
+  if (ss->record) HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, ss->slot, 0));
   double* shift = nullptr;
-  if (warm) {
-    // guess T_{n+1} from (T_n, T_{n-1}, E_n); apply_guess also moves T_n into T_prev
+  if (ss->warm) {
     HIP_TRY(hipMemsetAsync(ctx->nnB.fallbacks, 0, sizeof(int), ctx->stream));
     HIP_TRY(nn_predict(ctx->stream, ctx->g, ctx->nnL, ctx->nnB, ctx->T, ctx->Tprev, ctx->E));
     shift = ctx->s.warm == BTE_WARM_T_SHIFT ? ctx->nn_shift : nullptr;
@@ -360,27 +379,14 @@ int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
                            ctx->stream));
   }
   ctx->first_shift = shift;
-  HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
-  for (int j = 0; j < limit; ++j) {
-    int rc = enqueue_iteration(ctx, j, check ? 0 : fixed);
-    if (rc != BTE_OK) return rc;
-    if (check) {
-      // Keep one iteration queued ahead of the convergence test so the device
-      // never waits for the host; a surplus iteration is a no-op on the device.
-      HIP_TRY(hipMemcpyAsync(&ctx->host_ring[j % kRing], ctx->ctl, sizeof(Control),
-                             hipMemcpyDeviceToHost, ctx->stream));
-      HIP_TRY(hipEventRecord(ctx->ring_ev[j % kRing], ctx->stream));
-      if (j >= 1) {
-        HIP_TRY(hipEventSynchronize(ctx->ring_ev[(j - 1) % kRing]));
-        if (ctx->host_ring[(j - 1) % kRing].converged) break;
-      }
-    }
-  }
-  Control fin;
-  HIP_TRY(hipMemcpyAsync(&ctx->host_ring[0], ctx->ctl, sizeof(Control), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
-  fin = ctx->host_ring[0];
+  return BTE_OK;
+}
+
+// Everything after the inner loop, given the final control words: error
+// report, sweep timing, I^{n+1} <- newest iterate, the network's training
+// target and training, statistics.
+int step_finish(bte_ctx* ctx, const StepState& ss, const Control& fin, bte_step_stats* st) {
+  const int nc = ctx->s.nc;
   if (fin.err_cell != INT_MAX) {
     const int P = fin.err_cell;
     const int x = P % ctx->s.nx, y = (P / ctx->s.nx) % ctx->s.ny, z = P / (ctx->s.nx * ctx->s.ny);
@@ -400,15 +406,15 @@ int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
   // the newest iterate becomes I^{n+1}
   void*& last = ((fin.k - 1) & 1) ? ctx->Ib : ctx->Ia;
   std::swap(ctx->In, last);
-  int trained = 0;
+  int trained = 0, fallbacks = 0;
   double loss = 0.0;
-  if (warm) {
+  if (ss.warm) {
     HIP_TRY(hipMemcpyAsync(&fallbacks, ctx->nnB.fallbacks, sizeof(int), hipMemcpyDeviceToHost,
                            ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
   }
-  if (record) {
-    HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, slot, 1));
+  if (ss.record) {
+    HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, ss.slot, 1));
     ctx->nn_nrec += 1;
     if (ctx->nn_nrec == ctx->s.nn_rec) {
       int rc = nn_train(ctx, &loss);
@@ -420,16 +426,44 @@ int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
     st->inner = fin.k;
     st->newton_max = fin.newton_max;
     st->res = fin.res;
-    st->converged = explicit_mode || (fixed > 0 ? fin.k >= fixed : fin.res <= ctx->opt.tol);
-    st->warm = warm ? 1 : 0;
+    st->converged =
+        ss.explicit_mode || (ss.fixed > 0 ? fin.k >= ss.fixed : fin.res <= ctx->opt.tol);
+    st->warm = ss.warm ? 1 : 0;
     st->fallbacks = fallbacks;
     st->trained = trained;
     st->nn_loss = loss;
   }
-  if (!explicit_mode && fixed <= 0 && fin.res > ctx->opt.tol && ctx->opt.fail_on_notconv)
+  if (!ss.explicit_mode && ss.fixed <= 0 && fin.res > ctx->opt.tol && ctx->opt.fail_on_notconv)
     return fail(BTE_E_NOTCONV, "inner iteration hit max_inner=%d with res=%g > tol=%g",
                 ctx->opt.max_inner, fin.res, ctx->opt.tol);
   return BTE_OK;
+}
+
+int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
+  StepState ss;
+  int rc = step_begin(ctx, fixed, &ss);
+  if (rc != BTE_OK) return rc;
+  HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
+  for (int j = 0; j < ss.limit; ++j) {
+    rc = enqueue_iteration(ctx, j, ss.check ? 0 : fixed);
+    if (rc != BTE_OK) return rc;
+    if (ss.check) {
+      // Keep one iteration queued ahead of the convergence test so the device
+      // never waits for the host; a surplus iteration is a no-op on the device.
+      HIP_TRY(hipMemcpyAsync(&ctx->host_ring[j % kRing], ctx->ctl, sizeof(Control),
+                             hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(hipEventRecord(ctx->ring_ev[j % kRing], ctx->stream));
+      if (j >= 1) {
+        HIP_TRY(hipEventSynchronize(ctx->ring_ev[(j - 1) % kRing]));
+        if (ctx->host_ring[(j - 1) % kRing].converged) break;
+      }
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(&ctx->host_ring[0], ctx->ctl, sizeof(Control), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  const Control fin = ctx->host_ring[0];
+  return step_finish(ctx, ss, fin, st);
 }
 
 }  // namespace
@@ -887,5 +921,355 @@ int bte_destroy(bte_ctx* ctx) {
 }
 
 const char* bte_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------- autotuner
+static std::string tune_key(const bte_ctx* ctx) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "sweep dim=%d n=%dx%dx%d dirs=%d bands=%d prec=%d", ctx->s.dim,
+           ctx->s.nx, ctx->s.ny, ctx->s.nz, ctx->s.nd, ctx->s.nb, ctx->opt.precision);
+  return buf;
+}
+
+static void apply_plan(bte_ctx* ctx, const SweepPlan& pl) {
+  ctx->s.plan = pl;
+  ctx->g.ndg = pl.ndg;
+}
+
+int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* ndg_out,
+                 double* ms_out) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
+  const std::string key = tune_key(ctx);
+  const int ry_only = (ry_out && (*ry_out == 4 || *ry_out == 8)) ? *ry_out : 0;
+  SweepPlan best = ctx->s.plan;
+  double best_ms = -1.0;
+  bool cached = false;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[256];
+      while (fgets(line, sizeof line, f)) {
+        const char* sep = strstr(line, " -> ");
+        if (!sep || std::string(line, sep - line) != key) continue;
+        int ry = 0, ndg = 0;
+        double ms = 0.0;
+        if (sscanf(sep + 4, "ry=%d ndg=%d ms=%lf", &ry, &ndg, &ms) == 3 &&
+            (ry_only == 0 || ry == ry_only)) {
+          const SweepPlan pl = make_sweep_plan(ctx->s.dim, ctx->s.nx, ctx->s.ny, ctx->s.nz,
+                                               ctx->s.nd, ctx->s.nb, ry, ndg, ctx->s.plan.kind);
+          if (pl.ndg <= ctx->s.ndg_cap && pl.nparts <= ctx->s.nparts_cap) {
+            best = pl;
+            best_ms = ms;
+            cached = true;
+          }
+        }
+      }
+      fclose(f);
+    }
+  }
+  if (!cached && ctx->s.plan.kind == kSweepColumnWalk2D) {
+    // time every candidate layout on this context's own state: sweeps write only
+    // the iterate buffers and partials, so the state is untouched
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int ndgs[] = {1, 2, 4, 8, 16};
+    for (int ry : {4, 8}) {
+      if (ry_only != 0 && ry != ry_only) continue;
+      for (int nd_try : ndgs) {
+        const SweepPlan pl = make_sweep_plan(ctx->s.dim, ctx->s.nx, ctx->s.ny, ctx->s.nz,
+                                             ctx->s.nd, ctx->s.nb, ry, nd_try, kSweepColumnWalk2D);
+        if (pl.ndg != nd_try || pl.ndg > ctx->s.ndg_cap || pl.nparts > ctx->s.nparts_cap) continue;
+        apply_plan(ctx, pl);
+        HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
+        ctx->first_shift = nullptr;
+        int rc = ctx->opt.precision == BTE_FP64
+                     ? enqueue_sweep<double>(ctx, ctx->In, ctx->Ia, nullptr)
+                     : enqueue_sweep<float>(ctx, ctx->In, ctx->Ia, nullptr);
+        if (rc != BTE_OK) return rc;
+        HIP_TRY(hipEventRecord(e0, ctx->stream));
+        for (int r = 0; r < 3; ++r) {
+          rc = ctx->opt.precision == BTE_FP64
+                   ? enqueue_sweep<double>(ctx, ctx->In, ctx->Ia, nullptr)
+                   : enqueue_sweep<float>(ctx, ctx->In, ctx->Ia, nullptr);
+          if (rc != BTE_OK) return rc;
+        }
+        HIP_TRY(hipEventRecord(e1, ctx->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= 3.f;
+        if (best_ms < 0.0 || ms < best_ms) {
+          best_ms = ms;
+          best = pl;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path) {
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "%s -> ry=%d ndg=%d ms=%.6f\n", key.c_str(), best.ry, best.ndg, best_ms);
+        fclose(f);
+      }
+    }
+  }
+  apply_plan(ctx, best);
+  HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ry_out) *ry_out = best.ry;
+  if (ndg_out) *ndg_out = best.ndg;
+  if (ms_out) *ms_out = best_ms;
+  return BTE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+struct bte_batch {
+  std::vector<bte_ctx*> ctx;
+  hipStream_t stream;
+  int precision;
+  BatchCtx* d_ctx;
+  BatchCtx* h_ctx;  // pinned staging
+  BatchItem* d_items;
+  int n2d, n3d;
+  BatchControl* d_bc;
+  BatchControl* h_bc;  // pinned
+  Control* h_ctl;      // pinned, one per geometry
+  int sweep_blocks[2];
+  int temp_blocks;
+  int max_inner;
+  bool use_graph;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipEvent_t ev[kRing];
+};
+
+namespace {
+
+int batch_fail_free(bte_batch* b, int code) {
+  bte_batch_destroy(b);
+  return code;
+}
+
+// One iteration of every geometry, as eager launches or as the captured graph.
+int batch_enqueue_iteration(bte_batch* b) {
+  bte_ctx* ctx = nullptr;
+  if (b->use_graph) {
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  } else {
+    HIP_TRY(launch_batch_iteration(b->stream, b->precision, b->d_ctx, (int)b->ctx.size(),
+                                   b->d_items, b->n2d, b->n3d, b->d_bc, b->sweep_blocks,
+                                   b->temp_blocks));
+    HIP_TRY(hipMemcpyAsync(b->h_bc, b->d_bc, sizeof(BatchControl), hipMemcpyDeviceToHost,
+                           b->stream));
+  }
+  return BTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out) {
+  bte_ctx* ctx = nullptr;
+  if (!out || n < 1 || !ctxs) return fail(BTE_E_INVAL, "need at least one context");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    const bte_ctx* c = ctxs[i];
+    if (!c || c->poisoned) return fail(BTE_E_INVAL, "context %d is null or poisoned", i);
+    if (c->stream != ctxs[0]->stream) return fail(BTE_E_INVAL, "contexts must share one stream");
+    if (c->opt.precision != ctxs[0]->opt.precision)
+      return fail(BTE_E_INVAL, "contexts must share one precision");
+    if (c->opt.scheme != BTE_IMPLICIT_JACOBI)
+      return fail(BTE_E_INVAL, "batches run the implicit scheme");
+    if (c->s.warm == BTE_WARM_T_SHIFT)
+      return fail(BTE_E_INVAL, "batches seed warm starts through the temperature only");
+    if (c->s.plan.kind == kSweepColumnWalk2D && c->s.plan.ry != 4)
+      return fail(BTE_E_INVAL, "batches need the 4-row sweep layout (context %d)", i);
+    if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(BTE_E_INVAL, "context %d appears twice", i);
+  }
+  bte_batch* b = new (std::nothrow) bte_batch();
+  if (!b) return fail(BTE_E_NOMEM, "out of host memory");
+  b->ctx.assign(ctxs, ctxs + n);
+  b->stream = ctxs[0]->stream;
+  b->precision = ctxs[0]->opt.precision;
+  b->use_graph = use_graph != 0 && b->stream != nullptr;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  for (auto& e : b->ev) e = nullptr;
+  b->max_inner = 0;
+  // work list: 2D items then 3D items, each ordered largest geometry first
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    const double wa = (double)ctxs[a]->s.nc * ctxs[a]->s.nd * ctxs[a]->s.nb;
+    const double wc = (double)ctxs[c]->s.nc * ctxs[c]->s.nd * ctxs[c]->s.nb;
+    return wa > wc;
+  });
+  std::vector<BatchItem> items2, items3;
+  for (int i : order) {
+    const SweepPlan& pl = ctxs[i]->s.plan;
+    auto& dst = pl.kind == kSweepColumnWalk2D ? items2 : items3;
+    const int nz = pl.kind == kSweepColumnWalk2D ? pl.ndg : 1;
+    for (int bz = 0; bz < nz; ++bz)
+      for (int by = 0; by < ctxs[i]->s.nb; ++by)
+        for (int bx = 0; bx < pl.ntiles; ++bx) dst.push_back(BatchItem{i, bx, by, bz});
+    b->max_inner = std::max(b->max_inner, ctxs[i]->opt.max_inner);
+  }
+  b->n2d = (int)items2.size();
+  b->n3d = (int)items3.size();
+  items2.insert(items2.end(), items3.begin(), items3.end());
+  int cus = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  b->sweep_blocks[0] = cus * batch_sweep_occupancy(b->precision, true);
+  b->sweep_blocks[1] = cus * batch_sweep_occupancy(b->precision, false);
+  int blocks = 0;
+  for (int i = 0; i < n; ++i) blocks += (ctxs[i]->s.nc + 31) / 32;
+  b->temp_blocks = blocks;
+#define BATCH_TRY(expr)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      fail(BTE_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+      return batch_fail_free(b, BTE_E_DEVICE);                                        \
+    }                                                                                 \
+  } while (0)
+  b->d_ctx = nullptr;
+  b->h_ctx = nullptr;
+  b->d_items = nullptr;
+  b->d_bc = nullptr;
+  b->h_bc = nullptr;
+  b->h_ctl = nullptr;
+  BATCH_TRY(hipMalloc((void**)&b->d_ctx, sizeof(BatchCtx) * n));
+  BATCH_TRY(hipHostMalloc((void**)&b->h_ctx, sizeof(BatchCtx) * n));
+  BATCH_TRY(hipMalloc((void**)&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items2.size())));
+  BATCH_TRY(hipMalloc((void**)&b->d_bc, sizeof(BatchControl)));
+  BATCH_TRY(hipHostMalloc((void**)&b->h_bc, sizeof(BatchControl)));
+  BATCH_TRY(hipHostMalloc((void**)&b->h_ctl, sizeof(Control) * n));
+  for (auto& e : b->ev) BATCH_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (!items2.empty())
+    BATCH_TRY(hipMemcpyAsync(b->d_items, items2.data(), sizeof(BatchItem) * items2.size(),
+                             hipMemcpyHostToDevice, b->stream));
+  BATCH_TRY(hipStreamSynchronize(b->stream));
+  if (b->use_graph) {
+    BATCH_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t e1 = launch_batch_iteration(b->stream, b->precision, b->d_ctx, n, b->d_items,
+                                                 b->n2d, b->n3d, b->d_bc, b->sweep_blocks,
+                                                 b->temp_blocks);
+    const hipError_t e2 = hipMemcpyAsync(b->h_bc, b->d_bc, sizeof(BatchControl),
+                                         hipMemcpyDeviceToHost, b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e3 = hipStreamEndCapture(b->stream, &g);
+    b->graph = g;
+    BATCH_TRY(e1);
+    BATCH_TRY(e2);
+    BATCH_TRY(e3);
+    BATCH_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+#undef BATCH_TRY
+  *out = b;
+  (void)ctx;
+  return BTE_OK;
+}
+
+int bte_batch_step(bte_batch* b, int nsteps, bte_step_stats* stats) {
+  bte_ctx* ctx = nullptr;
+  if (!b) return fail(BTE_E_INVAL, "null batch");
+  if (nsteps < 0) return fail(BTE_E_INVAL, "nsteps must be >= 0");
+  const int n = (int)b->ctx.size();
+  std::vector<StepState> ss(n);
+  for (int step = 0; step < nsteps; ++step) {
+    for (int i = 0; i < n; ++i) {
+      ctx = b->ctx[i];
+      if (ctx->poisoned) return fail(BTE_E_DEVICE, "context %d is poisoned", i);
+      int rc = step_begin(ctx, 0, &ss[i]);
+      if (rc != BTE_OK) return rc;
+      BatchCtx& d = b->h_ctx[i];
+      memset(&d, 0, sizeof d);
+      d.sp64.g = ctx->g;
+      d.sp64.t = ctx->t;
+      d.sp64.In = static_cast<const double*>(ctx->In);
+      d.sp64.I0 = ctx->I0;
+      d.sp64.S = ctx->S;
+      d.sp64.part = ctx->part;
+      d.sp64.ctl = ctx->ctl;
+      d.sp64.inv_dt = 1.0 / ctx->opt.dt;
+      d.sp64.shift = nullptr;
+      d.sp32.g = ctx->g;
+      d.sp32.t = ctx->t;
+      d.sp32.In = static_cast<const float*>(ctx->In);
+      d.sp32.I0 = ctx->I0;
+      d.sp32.S = ctx->S;
+      d.sp32.part = ctx->part;
+      d.sp32.ctl = ctx->ctl;
+      d.sp32.inv_dt = 1.0 / ctx->opt.dt;
+      d.sp32.shift = nullptr;
+      d.plan = ctx->s.plan;
+      d.precision = ctx->opt.precision;
+      d.in_idx = 0;
+      d.F[0] = ctx->In;
+      d.F[1] = ctx->Ia;
+      d.F[2] = ctx->Ib;
+      d.I0 = ctx->I0;
+      d.S = ctx->S;
+      d.part = ctx->part;
+      d.T = ctx->T;
+      d.E = ctx->E;
+      d.ctl = ctx->ctl;
+      d.tol = ctx->opt.tol;
+      d.max_inner = ctx->opt.max_inner;
+      d.fixed_k = 0;
+      d.cell_block0 = (i == 0) ? 0 : b->h_ctx[i - 1].cell_block0 + b->h_ctx[i - 1].cell_blocks;
+      d.cell_blocks = (ctx->s.nc + 31) / 32;
+    }
+    ctx = nullptr;
+    HIP_TRY(hipMemcpyAsync(b->d_ctx, b->h_ctx, sizeof(BatchCtx) * n, hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(launch_batch_reset(b->stream, b->d_ctx, n, b->d_bc));
+    for (int j = 0; j < b->max_inner; ++j) {
+      int rc = batch_enqueue_iteration(b);
+      if (rc != BTE_OK) return rc;
+      HIP_TRY(hipEventRecord(b->ev[j % kRing], b->stream));
+      if (j >= 1) {
+        // the device runs one iteration ahead; the active count only falls
+        HIP_TRY(hipEventSynchronize(b->ev[(j - 1) % kRing]));
+        if (b->h_bc->active == 0) break;
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      HIP_TRY(hipMemcpyAsync(&b->h_ctl[i], b->ctx[i]->ctl, sizeof(Control), hipMemcpyDeviceToHost,
+                             b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < n; ++i) {
+      const Control fin = b->h_ctl[i];
+      int rc = step_finish(b->ctx[i], ss[i], fin, stats ? &stats[(size_t)step * n + i] : nullptr);
+      if (rc != BTE_OK) return rc;
+    }
+  }
+  return BTE_OK;
+}
+
+int bte_batch_destroy(bte_batch* b) {
+  if (!b) return BTE_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->d_ctx) (void)hipFree(b->d_ctx);
+  if (b->h_ctx) (void)hipHostFree(b->h_ctx);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_bc) (void)hipFree(b->d_bc);
+  if (b->h_bc) (void)hipHostFree(b->h_bc);
+  if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+  delete b;
+  return BTE_OK;
+}
 
 }  // extern "C"

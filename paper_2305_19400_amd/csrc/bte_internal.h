@@ -87,6 +87,26 @@ struct Tables {
   int wall_nf[6];
 };
 
+// Everything one sweep launch reads: mesh, tables, the three intensity
+// fields of the iteration (current iterate, step start, new iterate), the
+// equilibrium at the current temperature, the outputs.
+template <typename Real>
+struct SweepParams {
+  Geometry g;
+  Tables t;
+  const Real* __restrict__ Ik;
+  const Real* __restrict__ In;
+  Real* __restrict__ Iout;
+  const double* __restrict__ I0;
+  double* __restrict__ S;
+  double* __restrict__ part;
+  const Control* ctl;
+  double inv_dt;
+  // first sweep of a warm-started step: I^(0) = I^n + shift[b][P] (isotropic
+  // equilibrium shift at the guessed temperature); null otherwise
+  const double* __restrict__ shift;
+};
+
 // Launchers (bte_kernels.hip).  All enqueue on `stream` and return the launch status.
 template <typename Real>
 hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
@@ -102,6 +122,49 @@ hipError_t launch_control(hipStream_t stream, int nparts, const double* part, do
                           Control* ctl);
 
 hipError_t launch_reset(hipStream_t stream, Control* ctl);
+
+// ---------------------------------------------------------------- batches
+// One geometry of a batched step as the batched kernels see it.  The three
+// intensity fields F[] and in_idx (which one holds I^n) let the kernels pick
+// each inner iteration's source and destination from the device iteration
+// count, so one captured launch sequence serves every iteration.
+struct BatchCtx {
+  SweepParams<double> sp64;  // sweep parameters (the one matching the storage is used);
+  SweepParams<float> sp32;   // Ik / Iout are rewritten on the device every iteration
+  SweepPlan plan;
+  int precision;  // 0 FP64, 1 FP32 storage
+  int in_idx;
+  void* F[3];
+  double* I0;
+  double* S;
+  double* part;
+  double* T;
+  double* E;
+  Control* ctl;
+  double tol;
+  int max_inner, fixed_k;
+  int cell_block0, cell_blocks;  // blocks of the batched temperature kernel
+};
+
+struct BatchItem {
+  int ctx, bx, by, bz;
+};
+
+struct BatchControl {
+  int next_item;  // persistent-sweep work counter (2D list)
+  int iteration;  // batched iterations completed
+  int active;     // geometries not yet converged after the last iteration
+  int pad;        // persistent-sweep work counter (3D list)
+};
+
+// One inner iteration of every geometry: persistent sweep over the work list,
+// temperature inversion, per-geometry control, active count (+ reset of the
+// work counter for the next iteration).
+hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* ctxs,
+                                  int nctx, const BatchItem* items, int n2d, int n3d,
+                                  BatchControl* bc, const int sweep_blocks[2], int temp_blocks);
+hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, BatchControl* bc);
+int batch_sweep_occupancy(int precision, bool walk2d);
 
 hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* T, double* I0, double* E);

@@ -19,6 +19,25 @@ __device__ __forceinline__ double equilibrium(double C, double xf, double T) {
   return C / expm1(xf / T);
 }
 
+// ---------------------------------------------------------------- control flags
+// The control word is read through a generic pointer, which the compiler must
+// treat as possibly divergent.  Every branch that decides whether a workgroup
+// reaches a barrier reads it through this helper: readfirstlane makes the
+// value (and so the branch) wave-uniform, which keeps __syncthreads() in
+// uniform control flow.  Without it the structurizer may nest a persistent
+// loop so that most lanes circle the barrier while the lane that advances the
+// work counter waits outside the inner loop.
+__device__ __forceinline__ bool step_done(const Control* ctl) {
+  return __builtin_amdgcn_readfirstlane(ctl->converged) != 0;
+}
+
+// The sweep, temperature and control bodies are inlined into both the
+// per-geometry kernels and the batched persistent kernels.  They set
+// "fp contract(on)": a multiply is fused into an add only inside one source
+// expression, never across statements at the compiler's discretion, so every
+// kernel that inlines a body rounds exactly alike and batched results equal
+// single-geometry results bit for bit.
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
   // Butterfly over the 64 lanes; the order is fixed, so results are reproducible.
@@ -70,22 +89,6 @@ __device__ __forceinline__ Real encode(double iref, double I) {
 }
 
 // ---------------------------------------------------------------- sweep
-template <typename Real>
-struct SweepParams {
-  Geometry g;
-  Tables t;
-  const Real* __restrict__ Ik;
-  const Real* __restrict__ In;
-  Real* __restrict__ Iout;
-  const double* __restrict__ I0;
-  double* __restrict__ S;
-  double* __restrict__ part;
-  const Control* ctl;
-  double inv_dt;
-  // first sweep of a warm-started step: I^(0) = I^n + shift[b][P] (isotropic
-  // equilibrium shift at the guessed temperature); null otherwise
-  const double* __restrict__ shift;
-};
 
 // v + shift[b][P] in the first sweep of a warm-started step, v otherwise.
 template <bool SHIFT, typename Real>
@@ -127,10 +130,11 @@ __device__ __forceinline__ double upwind_value(const SweepParams<Real>& p, const
 // Forward Euler passes I^k = I^n and scale = dt, which is Eq.
 // eq-conservation-discrete with the same upwind fluxes.
 template <typename Real, int DIM, bool SHIFT>
-__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Real> p) {
-  if (p.ctl->converged) return;
-  const int b = blockIdx.y;
-  const int P = blockIdx.x * kSweepBlock + threadIdx.x;
+__device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int bx, const int by,
+                                           const int gx) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
+  const int b = by;
+  const int P = bx * kSweepBlock + threadIdx.x;
   const Geometry& g = p.g;
   const bool active = P < g.nc;
   int x = 0, y = 0, z = 0;
@@ -210,10 +214,16 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Re
       a += red[0][i];
       c += red[1][i];
     }
-    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const size_t blk = (size_t)by * gx + bx;
     p.part[2 * blk] = a;
     p.part[2 * blk + 1] = c;
   }
+}
+
+template <typename Real, int DIM, bool SHIFT>
+__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Real> p) {
+  if (step_done(p.ctl)) return;
+  sweep_body<Real, DIM, SHIFT>(p, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ---------------------------------------------------------------- 2D column walk
@@ -293,15 +303,16 @@ __device__ __forceinline__ double wall_ghost(const SweepParams<Real>& p, const R
 // load and broadcast with readlane).  The per-(direction group, band, cell)
 // energy partials and per-workgroup norm partials are fused as in sweep_kernel.
 template <typename Real, int RY, bool SHIFT>
-__global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepParams<Real> p,
-                                                                   const int ntx, const int dgs) {
-  if (p.ctl->converged) return;
+__device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const int ntx,
+                                            const int dgs, const int bx, const int by,
+                                            const int bz, const int gx, const int gy) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
   const Geometry& g = p.g;
   const int nx = g.nx, ny = g.ny;
-  const int tx = blockIdx.x % ntx;
-  const int ty = blockIdx.x / ntx;
-  const int b = blockIdx.y;
-  const int dg = blockIdx.z;
+  const int tx = bx % ntx;
+  const int ty = bx / ntx;
+  const int b = by;
+  const int dg = bz;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x0 = tx * 64;
@@ -457,10 +468,18 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
       a += red[0][i];
       c += red[1][i];
     }
-    const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const size_t blk = ((size_t)bz * gy + by) * gx + bx;
     p.part[2 * blk] = a;
     p.part[2 * blk + 1] = c;
   }
+}
+
+template <typename Real, int RY, bool SHIFT>
+__global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepParams<Real> p,
+                                                                   const int ntx, const int dgs) {
+  if (step_done(p.ctl)) return;
+  walk2d_body<Real, RY, SHIFT>(p, ntx, dgs, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
+                               gridDim.y);
 }
 
 SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int ndg,
@@ -587,14 +606,14 @@ __device__ __forceinline__ void relation_part(const Tables& t, int nb, int l, do
 // partials, invert the temperature relation by Newton from the current T
 // (accept-first, quadratic convergence; Sec. 2.2 and Sec. 3.2 temperature
 // update), then refresh the equilibrium intensities I0[b][P] for the next sweep.
-__global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
-                                                          const double* __restrict__ S,
-                                                          double* __restrict__ T,
-                                                          double* __restrict__ I0,
-                                                          double* __restrict__ E, Control* ctl) {
-  if (ctl->converged) return;
+__device__ __forceinline__ void temperature_body(const Geometry& g, const Tables& t,
+                                                 const double* __restrict__ S,
+                                                 double* __restrict__ T, double* __restrict__ I0,
+                                                 double* __restrict__ E, Control* ctl,
+                                                 const int bx) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
   const int l = threadIdx.x % kLanesPerCell;
-  const int P = blockIdx.x * (256 / kLanesPerCell) + threadIdx.x / kLanesPerCell;
+  const int P = bx * (256 / kLanesPerCell) + threadIdx.x / kLanesPerCell;
   const bool active = P < g.nc;
   const int Pc = active ? P : 0;
   const size_t ncp = (size_t)g.ncp;
@@ -647,6 +666,15 @@ __global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
   }
 }
 
+__global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
+                                                          const double* __restrict__ S,
+                                                          double* __restrict__ T,
+                                                          double* __restrict__ I0,
+                                                          double* __restrict__ E, Control* ctl) {
+  if (step_done(ctl)) return;
+  temperature_body(g, t, S, T, I0, E, ctl, blockIdx.x);
+}
+
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* S, double* T, double* I0, double* E, Control* ctl) {
   const int cells_per_block = 256 / kLanesPerCell;
@@ -660,14 +688,12 @@ hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Table
 // increment norm res = ||I^{k+1}-I^k|| / ||I^{k+1}-I^n|| (0/0 -> 0) and decides
 // whether the inner loop is finished; later kernels of the step then return
 // immediately.
-__global__ __launch_bounds__(kReduceBlock) void control_kernel(int nparts,
-                                                               const double* __restrict__ part,
-                                                               double vol, int fixed_k,
-                                                               int max_inner, double tol,
-                                                               int explicit_mode, Control* ctl) {
+__device__ __forceinline__ void control_body(int nparts, const double* __restrict__ part,
+                                             double vol, int fixed_k, int max_inner, double tol,
+                                             int explicit_mode, Control* ctl) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
   __shared__ double sn[kReduceBlock];
   __shared__ double sd[kReduceBlock];
-  if (ctl->converged) return;
   double n = 0.0, d = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kReduceBlock) {
     n += part[2 * i];
@@ -699,6 +725,15 @@ __global__ __launch_bounds__(kReduceBlock) void control_kernel(int nparts,
     ctl->den = den;
     ctl->converged = done;
   }
+}
+
+__global__ __launch_bounds__(kReduceBlock) void control_kernel(int nparts,
+                                                               const double* __restrict__ part,
+                                                               double vol, int fixed_k,
+                                                               int max_inner, double tol,
+                                                               int explicit_mode, Control* ctl) {
+  if (step_done(ctl)) return;
+  control_body(nparts, part, vol, fixed_k, max_inner, tol, explicit_mode, ctl);
 }
 
 hipError_t launch_control(hipStream_t stream, int nparts, const double* part, double vol,
@@ -840,5 +875,179 @@ template hipError_t launch_energy<double>(hipStream_t, const Geometry&, const Ta
                                           const double*, double*);
 template hipError_t launch_energy<float>(hipStream_t, const Geometry&, const Tables&,
                                          const float*, double*);
+
+}  // namespace bte
+
+namespace bte {
+
+// ---------------------------------------------------------------- batched
+template <typename Real>
+__device__ __forceinline__ const SweepParams<Real>& batch_params(const BatchCtx& c);
+template <>
+__device__ __forceinline__ const SweepParams<double>& batch_params<double>(const BatchCtx& c) {
+  return c.sp64;
+}
+template <>
+__device__ __forceinline__ const SweepParams<float>& batch_params<float>(const BatchCtx& c) {
+  return c.sp32;
+}
+
+// One work item of a batched sweep.  The geometry's parameters live in device
+// memory (the source / destination iterates are rewritten there after every
+// iteration), and batches seed warm starts through the temperature only (no
+// intensity shift).
+template <typename Real, bool WALK2D>
+__device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w) {
+  const SweepParams<Real>& p = batch_params<Real>(c);
+  const SweepPlan& pl = c.plan;
+  if constexpr (WALK2D)  // batches use 4 rows per wave
+    walk2d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+  else
+    sweep_body<Real, 3, false>(p, w.bx, w.by, pl.ntiles);
+}
+
+// Persistent sweep: each workgroup takes work items (geometry, tile, band,
+// direction group) from a shared counter until the list is exhausted; items of
+// geometries that have already converged are skipped.  The list is ordered
+// largest geometry first.
+//
+// The loop header is the barrier that publishes the claimed item, and thread 0
+// claims the next item at the end of an iteration.  With the claim at the top
+// of the loop instead, the compiler threads the "thread 0" condition of the
+// item's own final reduction into the next claim across the back-edge, which
+// makes the loop's continuation divergent: lanes other than thread 0 then
+// circle the barrier re-reading a stale item while thread 0 waits outside the
+// inner loop, and the kernel never finishes.
+template <typename Real, bool WALK2D>
+__global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx* __restrict__ ctxs,
+                                                                  const BatchItem* __restrict__ items,
+                                                                  int nitems, int* next_item) {
+  __shared__ int item_s;
+  if (threadIdx.x == 0) item_s = atomicAdd(next_item, 1);
+  for (;;) {
+    __syncthreads();  // the claimed item is visible to every lane
+    // the item and everything derived from it are wave-uniform (scalar registers)
+    const int it = __builtin_amdgcn_readfirstlane(item_s);
+    __syncthreads();  // every lane has read it before thread 0 claims the next one
+    if (it >= nitems) break;
+    BatchItem w;
+    w.ctx = __builtin_amdgcn_readfirstlane(items[it].ctx);
+    w.bx = __builtin_amdgcn_readfirstlane(items[it].bx);
+    w.by = __builtin_amdgcn_readfirstlane(items[it].by);
+    w.bz = __builtin_amdgcn_readfirstlane(items[it].bz);
+    const BatchCtx& c = ctxs[w.ctx];
+    if (!step_done(c.ctl)) batch_item<Real, WALK2D>(c, w);
+    if (threadIdx.x == 0) item_s = atomicAdd(next_item, 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_temperature_kernel(const BatchCtx* __restrict__ ctxs,
+                                                                int nctx) {
+  const int blk = blockIdx.x;
+  int ci = 0;
+  while (ci + 1 < nctx && blk >= ctxs[ci + 1].cell_block0) ++ci;
+  const BatchCtx& c = ctxs[ci];
+  if (blk - c.cell_block0 >= c.cell_blocks || step_done(c.ctl)) return;
+  temperature_body(c.sp64.g, c.sp64.t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
+}
+
+__global__ __launch_bounds__(kReduceBlock) void batch_control_kernel(BatchCtx* ctxs) {
+  BatchCtx& c = ctxs[blockIdx.x];
+  if (step_done(c.ctl)) return;
+  control_body(c.plan.nparts, c.part, c.sp64.g.vol, c.fixed_k, c.max_inner, c.tol, 0, c.ctl);
+  if (threadIdx.x == 0) {
+    // next iteration reads the iterate just written and writes the other one
+    const int k = c.ctl->k;
+    const int ia = (c.in_idx + 1) % 3, ib = (c.in_idx + 2) % 3;
+    void* written = c.F[((k - 1) & 1) ? ib : ia];
+    void* other = c.F[((k - 1) & 1) ? ia : ib];
+    c.sp64.Ik = static_cast<const double*>(written);
+    c.sp64.Iout = static_cast<double*>(other);
+    c.sp32.Ik = static_cast<const float*>(written);
+    c.sp32.Iout = static_cast<float*>(other);
+  }
+}
+
+__global__ void batch_count_kernel(const BatchCtx* __restrict__ ctxs, int nctx, BatchControl* bc) {
+  if (threadIdx.x != 0) return;
+  int active = 0;
+  for (int i = 0; i < nctx; ++i) active += ctxs[i].ctl->converged ? 0 : 1;
+  bc->active = active;
+  bc->iteration += 1;
+  bc->next_item = 0;
+  bc->pad = 0;
+}
+
+__global__ void batch_reset_kernel(BatchCtx* ctxs, int nctx, BatchControl* bc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nctx) {
+    BatchCtx& c = ctxs[i];
+    const int ia = (c.in_idx + 1) % 3;
+    c.sp64.Ik = static_cast<const double*>(c.F[c.in_idx]);
+    c.sp64.Iout = static_cast<double*>(c.F[ia]);
+    c.sp32.Ik = static_cast<const float*>(c.F[c.in_idx]);
+    c.sp32.Iout = static_cast<float*>(c.F[ia]);
+    Control* ctl = c.ctl;
+    ctl->converged = 0;
+    ctl->k = 0;
+    ctl->newton_max = 0;
+    ctl->err_cell = INT_MAX;
+    ctl->res = 0.0;
+    ctl->num = 0.0;
+    ctl->den = 0.0;
+  }
+  if (i == 0) {
+    bc->next_item = 0;
+    bc->iteration = 0;
+    bc->active = nctx;
+    bc->pad = 0;
+  }
+}
+
+template <typename Real>
+static void launch_batch_sweeps(hipStream_t stream, const BatchCtx* ctxs, const BatchItem* items,
+                                int n2d, int n3d, BatchControl* bc, const int blocks[2]) {
+  // the 2D and 3D work lists are consumed by two persistent launches, each
+  // compiled for one kernel family so neither pays the other's registers
+  if (n2d > 0)
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, true>), dim3(blocks[0]), dim3(kSweepBlock), 0,
+                       stream, ctxs, items, n2d, &bc->next_item);
+  if (n3d > 0)
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, false>), dim3(blocks[1]), dim3(kSweepBlock), 0,
+                       stream, ctxs, items + n2d, n3d, &bc->pad);
+}
+
+hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* ctxs,
+                                  int nctx, const BatchItem* items, int n2d, int n3d,
+                                  BatchControl* bc, const int sweep_blocks[2], int temp_blocks) {
+  if (precision == 0) launch_batch_sweeps<double>(stream, ctxs, items, n2d, n3d, bc, sweep_blocks);
+  else launch_batch_sweeps<float>(stream, ctxs, items, n2d, n3d, bc, sweep_blocks);
+  hipLaunchKernelGGL(batch_temperature_kernel, dim3(temp_blocks), dim3(256), 0, stream, ctxs, nctx);
+  hipLaunchKernelGGL(batch_control_kernel, dim3(nctx), dim3(kReduceBlock), 0, stream, ctxs);
+  hipLaunchKernelGGL(batch_count_kernel, dim3(1), dim3(64), 0, stream, ctxs, nctx, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, BatchControl* bc) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3((nctx + 63) / 64), dim3(64), 0, stream, ctxs, nctx, bc);
+  return hipGetLastError();
+}
+
+int batch_sweep_occupancy(int precision, bool walk2d) {
+  int n = 0;
+  hipError_t e;
+  if (precision == 0)
+    e = walk2d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<double, true>,
+                                                              kSweepBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<double, false>,
+                                                              kSweepBlock, 0);
+  else
+    e = walk2d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<float, true>,
+                                                              kSweepBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<float, false>,
+                                                              kSweepBlock, 0);
+  if (e != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
 
 }  // namespace bte

@@ -337,6 +337,75 @@ def config_c4(seed: int = 4) -> Instance:
     return gaussian_3d(96, 96, 96, 20, 20, 40, seed, name="c4_3d96_d400_b55", nsteps=100)
 
 
+def hotspot_field(n, dim, rng, peak, sigma_cells):
+    """300 K body with one Gaussian hot spot whose centre lies in the middle half of
+    each axis; ``n`` is [nx, ny, nz] (nz = 1 in 2D)."""
+    nx, ny, nz = n
+    c = [rng.uniform(0.25 * m, 0.75 * m) for m in n[:dim]] + [0.5] * (3 - dim)
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
+                          indexing="ij")
+    r2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 if dim == 3 else \
+        (x - c[0]) ** 2 + (y - c[1]) ** 2
+    return (300.0 + peak * np.exp(-r2 / (2.0 * sigma_cells ** 2))).reshape(-1)
+
+
+def batch_geometry(rng: np.random.Generator, index: int, cells_range=(4e3, 2.6e5),
+                   dirs_range=(80, 400), freq_range=(8, 40), nsteps: int = 30) -> Instance:
+    """One member of the batched workload: 2D or 3D (equal odds), cell count
+    log-uniform in ``cells_range`` with a random aspect ratio, a product
+    direction set with N_d in ``dirs_range`` (even azimuthal count, so every wall
+    mirror maps the set onto itself), ``freq_range`` frequency bands of the
+    quadratic dispersion, one Gaussian hot spot (+10..50 K), and a random wall mix
+    (each wall isothermal at 300 K, specular or symmetry; at least one isothermal).
+    FP32 intensities, implicit steps of 1 ps to tolerance 1e-4."""
+    dim = int(rng.integers(2, 4))
+    cells = math.exp(rng.uniform(math.log(cells_range[0]), math.log(cells_range[1])))
+    if dim == 2:
+        ar = math.exp(rng.uniform(math.log(0.5), math.log(2.0)))
+        nx = max(4, int(round(math.sqrt(cells * ar))))
+        n = [nx, max(4, int(round(cells / nx))), 1]
+    else:
+        a = np.exp(rng.uniform(math.log(0.7), math.log(1.4), size=3))
+        a /= np.prod(a) ** (1.0 / 3.0)
+        side = cells ** (1.0 / 3.0)
+        n = [max(4, int(round(side * v))) for v in a]
+    n_polar = int(rng.integers(4, 21))
+    lo = 2 * math.ceil(dirs_range[0] / n_polar / 2)
+    hi = 2 * math.floor(dirs_range[1] / n_polar / 2)
+    n_az = int(2 * rng.integers(lo // 2, hi // 2 + 1))
+    n_freq = int(rng.integers(freq_range[0], freq_range[1] + 1))
+    bands = quadratic_bands(n_freq, rng)
+    s, w = product_quadrature(n_polar, n_az)
+    kinds = [int(rng.choice([WALL_ISOTHERMAL, WALL_SPECULAR, WALL_SYMMETRY], p=[0.5, 0.3, 0.2]))
+             for _ in range(2 * dim)]
+    if WALL_ISOTHERMAL not in kinds:
+        kinds[int(rng.integers(0, 2 * dim))] = WALL_ISOTHERMAL
+    kinds += [WALL_ISOTHERMAL] * (6 - 2 * dim)
+    peak = rng.uniform(10.0, 50.0)
+    sigma = rng.uniform(0.1, 0.25) * min(n[:dim])
+    T = hotspot_field(n, dim, rng, peak, sigma)
+    h = [1e-8] * dim
+    return make_instance(f"c5_{index:02d}_{dim}d_" + "x".join(str(v) for v in n[:dim]) +
+                         f"_d{n_polar * n_az}_f{n_freq}", dim, n, h, kinds,
+                         uniform_walls(n, dim, kinds, [300.0] * 6), T, s, w, bands,
+                         dt=1e-12, tol=1e-4, max_inner=200, nsteps=nsteps,
+                         precision=PRECISION_FP32_MIXED, seed=index)
+
+
+def config_c5(seed: int = 5, count: int = 64, cells_range=(4e3, 1.0e5),
+              nsteps: int = 30) -> List[Instance]:
+    """Batched workload: ``count`` independent 2D/3D geometries drawn by
+    ``batch_geometry`` from one seeded stream (cells log-uniform in
+    ``cells_range``, 80-400 directions, 8-40 frequency bands, hot spots and wall
+    mixes), FP32 intensities.
+
+    The default cell range is the reduced draw: with cells up to 2.6e5 the 64
+    geometries hold 3.2e10 DOF (381 GB for three FP32 intensity fields), more
+    than one GPU's 288 GB; up to 1.0e5 they hold 1.55e10 DOF (186 GB)."""
+    rng = np.random.default_rng(seed)
+    return [batch_geometry(rng, i, cells_range=cells_range, nsteps=nsteps) for i in range(count)]
+
+
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}
 
 

@@ -47,7 +47,7 @@ def test_workspace_size_c2():
     inst = inputs.config_c2()
     n = bte.bte_workspace_size(inst)
     field = inst.n_dof * 8
-    assert 3 * field <= n < 3 * field * 1.01 + (1 << 24)
+    assert 3 * field <= n < 3 * field * 1.02 + (1 << 28)  # fields + per-(group, band, cell) partials
     n32 = bte.bte_workspace_size(inst, precision=bte.BTE_FP32_MIXED)
     assert 3 * field // 2 <= n32 < n
 

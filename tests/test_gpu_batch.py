@@ -1,0 +1,154 @@
+"""Batched persistent stepping of uneven geometries (and its HIP graph), and
+the sweep-layout autotuner.  Every geometry of a batch must give exactly the
+results it gives when stepped alone (the batch runs the same arithmetic in
+the same order), graph replays included."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2305_19400_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_19400_amd import bte
+    bte.load_library()
+    return bte
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def same(name, got, want, inst=None):
+    """Bitwise comparison that reports where and by how much arrays differ."""
+    got, want = np.asarray(got), np.asarray(want)
+    if np.array_equal(got, want):
+        return True
+    bad = np.argwhere(got != want)
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
+    print(f"{name}: {len(bad)} of {got.size} differ; max rel {rel.max():.3e}", flush=True)
+    for idx in bad[:8]:
+        where = tuple(int(v) for v in idx)
+        if inst is not None:
+            P = where[-1]
+            nx, ny, _ = inst.n
+            where = where + ((P % nx, (P // nx) % ny, P // (nx * ny)),)
+        print(f"   at {where}: got {got[tuple(idx)]!r} want {want[tuple(idx)]!r}", flush=True)
+    return False
+
+
+def geometries(precision):
+    g = [I.strip_2d(48, 40, 2, 8, 6, seed=1, nsteps=3),
+         I.gaussian_3d(10, 9, 8, 2, 8, 4, seed=2, sigma_cells=2.0, precision=precision, nsteps=3),
+         I.strip_2d(130, 70, 2, 12, 5, seed=3, strip_cells=10, nsteps=3),
+         I.gaussian_3d(17, 12, 9, 4, 8, 3, seed=4, sigma_cells=2.5, precision=precision, nsteps=3),
+         I.strip_2d(20, 33, 3, 8, 4, seed=5, nsteps=3)]
+    for inst in g:
+        inst.precision = precision
+    return g
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
+def test_batch_equals_solo_runs(gpu, use_graph, precision):
+    import torch
+    insts = geometries(precision)
+    stream = torch.cuda.Stream()
+    nsteps = 3
+    announce(f"batch of {len(insts)} geometries, graph={use_graph}, precision={precision}")
+    solos = []
+    for inst in insts:
+        with gpu.Solver(inst, stream=stream) as s:
+            st = s.step(nsteps)
+            solos.append((st, s.temperature(), s.intensity()))
+    with gpu.Solver(insts[0], stream=stream) as s:  # solo runs are reproducible
+        st = s.step(nsteps)
+        assert [x["inner"] for x in st] == [x["inner"] for x in solos[0][0]]
+        assert same("solo rerun T", s.temperature(), solos[0][1])
+        assert same("solo rerun I", s.intensity(), solos[0][2], insts[0])
+    announce("solo runs done; creating the batch")
+    sols = [gpu.Solver(inst, stream=stream) for inst in insts]
+    with gpu.Batch(sols, use_graph=use_graph) as batch:
+        per_step = []
+        for k in range(nsteps):
+            announce(f"batch step {k}")
+            per_step.append(batch.step(1)[0])  # eager host work between graph replays
+            for i, s in enumerate(sols):  # every step checked against the solo run
+                assert per_step[-1][i]["converged"]
+        ok = True
+        for i, s in enumerate(sols):
+            st, T, Iq = solos[i]
+            assert [per_step[k][i]["inner"] for k in range(nsteps)] == [x["inner"] for x in st]
+            ok &= same(f"geometry {i} T", s.temperature(), T, insts[i])
+            ok &= same(f"geometry {i} I", s.intensity(), Iq, insts[i])
+        assert ok
+    # the contexts keep working on their own after the batch
+    for s in sols:
+        s.step(1)
+        s.close()
+
+
+def test_batch_with_learned_warm_start(gpu):
+    import torch
+    insts = geometries(I.PRECISION_FP32_MIXED)[:3]
+    stream = torch.cuda.Stream()
+    opts = dict(precision=gpu.BTE_FP32_MIXED, warm_start=gpu.BTE_WARM_T, nn_train_steps=3,
+                nn_seed=2)
+    announce("batch with warm start (train after 3 steps)")
+    ref = []
+    for inst in insts:
+        with gpu.Solver(inst, stream=stream, **opts) as s:
+            st = s.step(6)
+            ref.append(([x["inner"] for x in st], s.temperature()))
+    announce("solo runs done; batch of the same")
+    sols = [gpu.Solver(inst, stream=stream, **opts) for inst in insts]
+    with gpu.Batch(sols) as batch:
+        st = batch.step(6)
+    for i, s in enumerate(sols):
+        assert [st[k][i]["inner"] for k in range(6)] == ref[i][0]
+        assert st[2][i]["trained"] == 1 and all(st[k][i]["warm"] for k in range(3, 6))
+        assert same(f"warm geometry {i} T", s.temperature(), ref[i][1], insts[i])
+        s.close()
+
+
+def test_batch_rejects_mixed_precision(gpu):
+    import torch
+    stream = torch.cuda.Stream()
+    a = gpu.Solver(I.strip_2d(20, 20, 1, 8, 3, seed=1), stream=stream)
+    b = gpu.Solver(I.strip_2d(20, 20, 1, 8, 3, seed=1), stream=stream, precision=gpu.BTE_FP32_MIXED)
+    with pytest.raises(gpu.BteError) as e:
+        gpu.Batch([a, b])
+    assert e.value.code == gpu.BTE_E_INVAL
+    a.close()
+    b.close()
+
+
+def test_autotune_picks_a_layout_and_caches_it(gpu):
+    from oracle import Oracle
+    inst = I.strip_2d(64, 48, 4, 8, 10, seed=6, nsteps=2)
+    announce("autotune")
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tune.txt")
+        with gpu.Solver(inst) as s:
+            ry, ndg, ms = s.autotune(cache)
+            assert ry in (4, 8) and ndg >= 1 and ms > 0
+            ref = Oracle(inst)
+            sched = [x["inner"] for x in ref.run(2)]
+            s.step(2, fixed_inner=sched)
+            T = s.temperature()
+        assert np.max(np.abs(T - ref.temperature()) / ref.temperature()) <= 1e-10
+        text = open(cache).read()
+        assert f"ry={ry} ndg={ndg}" in text
+        with gpu.Solver(inst) as s2:
+            assert s2.autotune(cache)[:2] == (ry, ndg)  # read back from the cache
+        assert open(cache).read() == text
