@@ -39,6 +39,7 @@ struct Coef {
   double c[3];
   double scale;
 };
+static_assert(sizeof(Coef) == 4 * sizeof(double), "Coef is read as four contiguous doubles");
 
 // Direction flags: bit a set if s_{d,a} > 0, bit (4 + a) set if s_{d,a} < 0.
 __host__ __device__ inline bool dir_pos(int flags, int a) { return (flags >> a) & 1; }

@@ -253,6 +253,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* base, in
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufferWord3);
 }
 
+// Read-only table entry through the constant address space: with a
+// wave-uniform index the compiler emits a scalar load, which neither waits for
+// nor delays the vector loads of the intensity slabs.
+template <typename T>
+__device__ __forceinline__ T cld(const T* base, size_t i) {
+  return ((const __attribute__((address_space(4))) T*)base)[i];
+}
+__device__ __forceinline__ Coef cld_coef(const Coef* base, size_t i) {
+  const double* c = base[i].c;  // c[0], c[1], c[2], scale are contiguous doubles
+  Coef r;
+  r.c[0] = cld(c, 0);
+  r.c[1] = cld(c, 1);
+  r.c[2] = cld(c, 2);
+  r.scale = cld(c, 3);
+  return r;
+}
+
 template <typename Real>
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
 template <>
@@ -263,6 +280,20 @@ __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int
 template <>
 __device__ __forceinline__ double buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return (double)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, BTE_SLAB_LOAD_AUX));
+}
+
+// The stored value itself (no conversion), so that a load issued inside a
+// branch is not waited for inside it.
+template <typename Real>
+__device__ __forceinline__ Real buf_load_raw(__amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ double buf_load_raw<double>(__amdgpu_buffer_rsrc_t r, int voff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, BTE_SLAB_LOAD_AUX);
+  return __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]);
+}
+template <>
+__device__ __forceinline__ float buf_load_raw<float>(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, BTE_SLAB_LOAD_AUX));
 }
 
 template <typename Real>
@@ -329,7 +360,6 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   Real* __restrict__ Iob = p.Iout + band_off;
   const double inv_tau = p.t.inv_tau[b];
   const double iref = Storage<Real>::kDeviation ? p.t.Iref[b] : 0.0;
-  const Coef* __restrict__ coef = p.t.coef + (size_t)b * g.nd;
   const int slab_bytes = g.nc * (int)sizeof(Real);
   // Every lane and row addresses a valid cell: lanes past the mesh edge reuse
   // column x0 and rows past the mesh reuse this wave's first row (their values
@@ -338,9 +368,14 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   const int y0c = min(y0, ny - 1);
   const int row0 = (y0c * nx + x0) * (int)sizeof(Real);  // byte offset of (x0, y0)
   const int rowb = nx * (int)sizeof(Real);
-  int rowoff[RY];
+  int rowoff[RY];  // byte offset of (x0, row j) in a slab
+  int vrow[RY];    // this lane's byte offset in row j (offsets live in VGPRs, so the
+                   // slab loads never need a uniform register for them)
 #pragma unroll
-  for (int j = 0; j < RY; ++j) rowoff[j] = row0 + (j < nrows ? j : 0) * rowb;
+  for (int j = 0; j < RY; ++j) {
+    rowoff[j] = row0 + (j < nrows ? j : 0) * rowb;
+    vrow[j] = voff + rowoff[j];
+  }
 
   double I0r[RY], S[RY], Sc[RY], sh[RY];
   {
@@ -363,75 +398,108 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   }
   double num = 0.0, den = 0.0;
 
-  for (int d = d_begin; d < d_end; ++d) {
-    const Coef cf = coef[d];
-    const int fl = p.t.dflags[d];
-    const double wd = p.t.w[d];
-    const Real* __restrict__ sk = Ikb + (size_t)d * ncp;
-    const auto rk = slab_rsrc(sk, slab_bytes);
+  // Tile edges.  Lane j fetches the x-inflow value of row y0 + j (the
+  // neighbouring tile's column, or the wall ghost at the mesh edge); every lane
+  // fetches the y-inflow value of its column (the row just outside this wave's
+  // rows, or the wall ghost).  Which source applies is wave-uniform for a
+  // direction, so each edge is one load, issued with the slab loads before any
+  // of them is waited for.  Indices are clamped to valid cells.
+  const int jl = min(lane, max(nrows - 1, 0));
+  const int ye = min(y0 + jl, ny - 1);          // row whose x edge this lane fetches
+  const int xcol = colok ? x : x0;              // a valid column for every lane
+  const int last = min(63, nx - 1 - x0);        // last lane holding a mesh column
+  const bool wall_l = x0 == 0;                  // -x inflow of lane 0 is the wall
+  const bool wall_r = x0 + last == nx - 1;      // +x inflow of lane `last` is the wall
+  const int col_l = wall_l ? 0 : x0 - 1;
+  const int col_r = wall_r ? nx - 1 : x0 + 64;
+  const bool wall_p = y0 == 0;                  // +y-moving inflow through the -y wall
+  const bool wall_n = y0 + nrows >= ny;         // -y-moving inflow through the +y wall
+  const int row_p = wall_p ? 0 : min(y0 - 1, ny - 1);
+  const int row_n = wall_n ? ny - 1 : y0 + nrows;
+  double shx_l = 0.0, shx_r = 0.0, shy_p = 0.0, shy_n = 0.0;
+  if constexpr (SHIFT) {
+    const double* __restrict__ sb = p.shift + (size_t)b * ncp;
+    shx_l = sb[ye * nx + col_l];
+    shx_r = sb[ye * nx + col_r];
+    shy_p = sb[row_p * nx + xcol];
+    shy_n = sb[row_n * nx + xcol];
+  }
+
+  for (int d = d_begin; d < d_end && nrows > 0; ++d) {
+    const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
+    const int fl = cld(p.t.dflags, d);
+    const double wd = cld(p.t.w, d);
+    const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
+    const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
+    const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
     const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
     const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
+    Real rk_v[RY], rn_v[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      rk_v[j] = buf_load_raw<Real>(rk, vrow[j]);
+      rn_v[j] = buf_load_raw<Real>(rn, vrow[j]);
+    }
+    // Edges: both candidate sources are loaded without branching (the slab
+    // value -- neighbouring tile or, through a specular/symmetry wall, the wall
+    // cell in the mirrored direction -- and the isothermal wall's equilibrium,
+    // read from a valid placeholder address when the side is not isothermal),
+    // and wave-uniform selects pick one after every load of this direction has
+    // been issued.
+    const bool wx = xpos ? wall_l : wall_r;  // x inflow through a wall
+    const int sx = xpos ? 0 : 1;
+    const bool iso_x = wx && p.t.wall[sx] == 0;
+    const int dx_src = (wx && !iso_x) ? cld(p.t.mirror, (size_t)d) : d;
+    const Real ex_r = buf_load_raw<Real>(slab_rsrc(Ikb + (size_t)dx_src * ncp, slab_bytes),
+                                         (ye * nx + (xpos ? col_l : col_r)) * (int)sizeof(Real));
+    const double* __restrict__ wbx = iso_x ? p.t.wall_I0[sx] : p.t.w;  // valid either way
+    const double ex_w = wbx[iso_x ? (size_t)b * p.t.wall_nf[sx] + ye : 0];
+    const bool wy = ypos ? wall_p : wall_n;  // y inflow through a wall
+    const int sy = ypos ? 2 : 3;
+    const bool iso_y = wy && p.t.wall[sy] == 0;
+    const int dy_src = (wy && !iso_y) ? cld(p.t.mirror, (size_t)g.nd + d) : d;
+    const Real ey_r = buf_load_raw<Real>(slab_rsrc(Ikb + (size_t)dy_src * ncp, slab_bytes),
+                                         ((ypos ? row_p : row_n) * nx + xcol) * (int)sizeof(Real));
+    const double* __restrict__ wby = iso_y ? p.t.wall_I0[sy] : p.t.w;
+    const double ey_w = wby[iso_y ? (size_t)b * p.t.wall_nf[sy] + xcol : 0];
+    double ex = iso_x ? ex_w : decode(iref, ex_r);
+    double ey = iso_y ? ey_w : decode(iref, ey_r);
+    if constexpr (SHIFT) {
+      if (!iso_x) ex += xpos ? shx_l : shx_r;
+      if (!iso_y) ey += ypos ? shy_p : shy_n;
+    }
     double ik[RY], in[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      ik[j] = buf_load<Real>(rk, voff, rowoff[j]);
-      in[j] = buf_load<Real>(rn, voff, rowoff[j]);
-      if constexpr (Storage<Real>::kDeviation) {
-        ik[j] += iref;
-        in[j] += iref;
-      }
+      ik[j] = decode(iref, rk_v[j]);
+      in[j] = decode(iref, rn_v[j]);
       if constexpr (SHIFT) ik[j] += sh[j];
-    }
-    const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
-    const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
-    // y halo: the row just outside this wave's rows on the inflow side
-    double hy = 0.0;
-    if (colok && nrows > 0) {
-      if (ypos) {
-        hy = (y0 > 0) ? shifted<SHIFT>(decode(iref, sk[(size_t)(y0 - 1) * nx + x]), p, b, (y0 - 1) * nx + x)
-                      : wall_ghost<SHIFT>(p, Ikb, iref, 2, 1, b, d, x, x);
-      } else if (yneg) {
-        const int yh = y0 + nrows;
-        hy = (yh < ny) ? shifted<SHIFT>(decode(iref, sk[(size_t)yh * nx + x]), p, b, yh * nx + x)
-                       : wall_ghost<SHIFT>(p, Ikb, iref, 3, 1, b, d, (yh - 1) * nx + x, x);
-      }
-    }
-    // x halo column on the inflow side of the tile: lane j holds row y0 + j
-    double hx = 0.0;
-    if (lane < nrows && (xpos || xneg)) {
-      const int xh = xpos ? x0 - 1 : x0 + 64;
-      if (xh >= 0 && xh < nx)
-        hx = shifted<SHIFT>(decode(iref, sk[(size_t)(y0 + lane) * nx + xh]), p, b, (y0 + lane) * nx + xh);
     }
     // lane holding the x-upwind neighbour (direction sign is wave-uniform)
     const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const double nbr = __shfl(ik[j], src_lane, 64);
-      const double hxj = read_lane(hx, j);
+      const double exj = read_lane(ex, j);
       if (colok && j < nrows) {
-        const int y = y0 + j;
-        const int P = y * nx + x;
         const double v = ik[j];
         double acc = (in[j] - v) * p.inv_dt + (I0r[j] - v) * inv_tau;
         if (xpos) {
-          const double up = (x == 0) ? wall_ghost<SHIFT>(p, Ikb, iref, 0, 0, b, d, P, y)
-                                     : (lane == 0 ? hxj : nbr);
+          const double up = lane == 0 ? exj : nbr;
           acc += cf.c[0] * (up - v);
         } else if (xneg) {
-          const double up = (x == nx - 1) ? wall_ghost<SHIFT>(p, Ikb, iref, 1, 0, b, d, P, y)
-                                          : (lane == 63 ? hxj : nbr);
+          const double up = lane == last ? exj : nbr;
           acc += cf.c[0] * (up - v);
         }
         if (ypos) {
-          const double up = (j == 0) ? hy : ik[j > 0 ? j - 1 : 0];
+          const double up = (j == 0) ? ey : ik[j > 0 ? j - 1 : 0];
           acc += cf.c[1] * (up - v);
         } else if (yneg) {
-          const double up = (j == nrows - 1) ? hy : ik[j + 1 < RY ? j + 1 : RY - 1];
+          const double up = (j == nrows - 1) ? ey : ik[j + 1 < RY ? j + 1 : RY - 1];
           acc += cf.c[1] * (up - v);
         }
         const Real inew_r = encode<Real>(iref, v + acc * cf.scale);
-        buf_store<Real>(inew_r, ro, voff, rowoff[j]);
+        buf_store<Real>(inew_r, ro, vrow[j], 0);
         const double inew = decode(iref, inew_r);
         const double da = inew - v;
         const double dn = inew - in[j];
