@@ -90,143 +90,6 @@ __device__ __forceinline__ Real encode(double iref, double I) {
 
 // ---------------------------------------------------------------- sweep
 
-// v + shift[b][P] in the first sweep of a warm-started step, v otherwise.
-template <bool SHIFT, typename Real>
-__device__ __forceinline__ double shifted(double v, const SweepParams<Real>& p, int b, int P) {
-  if constexpr (SHIFT) return v + p.shift[(size_t)b * p.g.ncp + P];
-  else return v;
-}
-
-// Upwind value along one axis for a cell with coordinate `coord` along it:
-// the neighbour on the inflow side, or the wall ghost (Eq. eq-bdry) when the
-// inflow face is a wall face.
-template <bool SHIFT, typename Real>
-__device__ __forceinline__ double upwind_value(const SweepParams<Real>& p, const Real* slab,
-                                               const Real* band_base, double iref, int P, int b,
-                                               int d, int axis, bool from_minus, int coord,
-                                               int n, int stride, int face) {
-  if (from_minus) {
-    if (coord > 0) return shifted<SHIFT>(decode(iref, slab[P - stride]), p, b, P - stride);
-  } else {
-    if (coord < n - 1) return shifted<SHIFT>(decode(iref, slab[P + stride]), p, b, P + stride);
-  }
-  const int side = 2 * axis + (from_minus ? 0 : 1);
-  if (p.t.wall[side] == 0) {  // isothermal: equilibrium at the wall temperature
-    return p.t.wall_I0[side][(size_t)b * p.t.wall_nf[side] + face];
-  }
-  // specular / symmetry: the cell's own intensity in the mirrored direction
-  const int r = p.t.mirror[axis * p.g.nd + d];
-  return shifted<SHIFT>(decode(iref, band_base[(size_t)r * p.g.ncp + P]), p, b, P);
-}
-
-// One point-Jacobi sweep (or forward-Euler update) over every direction of one
-// band for a tile of kSweepBlock cells, fused with the per-(band, cell) energy
-// partial sum_d w_d I^{k+1} and the per-block pieces of the increment norms.
-//
-// For DOF (P, d, b) with current iterate I^k, step-start value I^n and
-// equilibrium I0 = I0_b(T_P^k) (Eq. eq-bte-fv, backward Euler, upwind faces):
-//   R = (I^n - I^k)/dt + (I0 - I^k)/tau_b + sum_axis c_axis (I_up,axis - I^k)
-//   I^{k+1} = I^k + R * scale,   scale = 1/(1/dt + 1/tau_b + sum_axis c_axis)
-// Forward Euler passes I^k = I^n and scale = dt, which is Eq.
-// eq-conservation-discrete with the same upwind fluxes.
-template <typename Real, int DIM, bool SHIFT>
-__device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int bx, const int by,
-                                           const int gx) {
-#pragma clang fp contract(on)  // fuse a*b+c only within one expression
-  const int b = by;
-  const int P = bx * kSweepBlock + threadIdx.x;
-  const Geometry& g = p.g;
-  const bool active = P < g.nc;
-  int x = 0, y = 0, z = 0;
-  if (active) {
-    x = P % g.nx;
-    const int r = P / g.nx;
-    y = r % g.ny;
-    z = r / g.ny;
-  }
-  const size_t ncp = (size_t)g.ncp;
-  const size_t band_off = (size_t)b * g.nd * ncp;
-  const Real* __restrict__ Ikb = p.Ik + band_off;
-  const Real* __restrict__ Inb = p.In + band_off;
-  Real* __restrict__ Iob = p.Iout + band_off;
-  const double I0P = active ? p.I0[(size_t)b * ncp + P] : 0.0;
-  const double inv_tau = p.t.inv_tau[b];
-  const double iref = Storage<Real>::kDeviation ? p.t.Iref[b] : 0.0;
-  const Coef* __restrict__ coef = p.t.coef + (size_t)b * g.nd;
-  const int face_x = y + g.ny * z;
-  const int face_y = x + g.nx * z;
-  const int face_z = x + g.nx * y;
-  const int sy = g.nx;
-  const int sz = g.nx * g.ny;
-
-  CompSum S;
-  double Splain = 0.0, num = 0.0, den = 0.0;
-  for (int d = 0; d < g.nd; ++d) {
-    const Coef cf = coef[d];
-    const int fl = p.t.dflags[d];
-    const double wd = p.t.w[d];
-    if (active) {
-      const Real* slab = Ikb + (size_t)d * ncp;
-      const double ik = shifted<SHIFT>(decode(iref, slab[P]), p, b, P);
-      const double in = decode(iref, Inb[(size_t)d * ncp + P]);
-      double acc = (in - ik) * p.inv_dt + (I0P - ik) * inv_tau;
-      if (dir_pos(fl, 0) || dir_neg(fl, 0)) {
-        const double up =
-            upwind_value<SHIFT>(p, slab, Ikb, iref, P, b, d, 0, dir_pos(fl, 0), x, g.nx, 1, face_x);
-        acc += cf.c[0] * (up - ik);
-      }
-      if (dir_pos(fl, 1) || dir_neg(fl, 1)) {
-        const double up =
-            upwind_value<SHIFT>(p, slab, Ikb, iref, P, b, d, 1, dir_pos(fl, 1), y, g.ny, sy, face_y);
-        acc += cf.c[1] * (up - ik);
-      }
-      if (DIM == 3 && (dir_pos(fl, 2) || dir_neg(fl, 2))) {
-        const double up =
-            upwind_value<SHIFT>(p, slab, Ikb, iref, P, b, d, 2, dir_pos(fl, 2), z, g.nz, sz, face_z);
-        acc += cf.c[2] * (up - ik);
-      }
-      const Real inew_r = encode<Real>(iref, ik + acc * cf.scale);
-      Iob[(size_t)d * ncp + P] = inew_r;
-      const double inew = decode(iref, inew_r);
-      const double da = inew - ik;
-      const double dn = inew - in;
-      if constexpr (Storage<Real>::kDeviation) S.add(wd * inew);
-      else Splain += wd * inew;
-      num += wd * da * da;
-      den += wd * dn * dn;
-    }
-  }
-  if (active) p.S[(size_t)b * ncp + P] = Storage<Real>::kDeviation ? S.value() : Splain;
-
-  __shared__ double red[2][kSweepBlock / 64];
-  num = wave_sum(num);
-  den = wave_sum(den);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][wave] = num;
-    red[1][wave] = den;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, c = 0.0;
-    for (int i = 0; i < kSweepBlock / 64; ++i) {
-      a += red[0][i];
-      c += red[1][i];
-    }
-    const size_t blk = (size_t)by * gx + bx;
-    p.part[2 * blk] = a;
-    p.part[2 * blk + 1] = c;
-  }
-}
-
-template <typename Real, int DIM, bool SHIFT>
-__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Real> p) {
-  if (step_done(p.ctl)) return;
-  sweep_body<Real, DIM, SHIFT>(p, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-// ---------------------------------------------------------------- 2D column walk
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
@@ -313,17 +176,142 @@ __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, BTE_SLAB_STORE_AUX);
 }
 
-// Ghost intensity on an inflow wall face (Eq. eq-bdry) for cell P of band b,
-// direction d: equilibrium at the wall temperature (isothermal) or the cell's
-// own intensity in the mirrored direction (specular / symmetry).
-template <bool SHIFT, typename Real>
-__device__ __forceinline__ double wall_ghost(const SweepParams<Real>& p, const Real* band_base,
-                                             double iref, int side, int axis, int b, int d, int P,
-                                             int face) {
-  if (p.t.wall[side] == 0) return p.t.wall_I0[side][(size_t)b * p.t.wall_nf[side] + face];
-  const int r = p.t.mirror[axis * p.g.nd + d];
-  return shifted<SHIFT>(decode(iref, band_base[(size_t)r * p.g.ncp + P]), p, b, P);
+// One point-Jacobi sweep (or forward-Euler update) over every direction of one
+// band for a tile of kSweepBlock cells, fused with the per-(band, cell) energy
+// partial sum_d w_d I^{k+1} and the per-block pieces of the increment norms.
+//
+// For DOF (P, d, b) with current iterate I^k, step-start value I^n and
+// equilibrium I0 = I0_b(T_P^k) (Eq. eq-bte-fv, backward Euler, upwind faces):
+//   R = (I^n - I^k)/dt + (I0 - I^k)/tau_b + sum_axis c_axis (I_up,axis - I^k)
+//   I^{k+1} = I^k + R * scale,   scale = 1/(1/dt + 1/tau_b + sum_axis c_axis)
+// Forward Euler passes I^k = I^n and scale = dt, which is Eq.
+// eq-conservation-discrete with the same upwind fluxes.
+template <typename Real, int DIM, bool SHIFT>
+__device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int bx, const int by,
+                                           const int gx) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
+  const int b = by;
+  const int P = bx * kSweepBlock + threadIdx.x;
+  const Geometry& g = p.g;
+  const bool active = P < g.nc;
+  const int Pc = active ? P : g.nc - 1;  // every lane addresses a valid cell
+  const int cx = Pc % g.nx;
+  const int cy = (Pc / g.nx) % g.ny;
+  const int cz = Pc / (g.nx * g.ny);
+  const size_t ncp = (size_t)g.ncp;
+  const size_t band_off = (size_t)b * g.nd * ncp;
+  const Real* __restrict__ Ikb = p.Ik + band_off;
+  const Real* __restrict__ Inb = p.In + band_off;
+  Real* __restrict__ Iob = p.Iout + band_off;
+  const double I0P = p.I0[(size_t)b * ncp + Pc];
+  const double inv_tau = cld(p.t.inv_tau, (size_t)b);
+  const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
+  const int slab_bytes = g.nc * (int)sizeof(Real);
+  const int voff = Pc * (int)sizeof(Real);
+  // Per axis: coordinate, extent, cell stride and wall-face index of this cell.
+  const int co[3] = {cx, cy, cz};
+  const int ext[3] = {g.nx, g.ny, g.nz};
+  const int str[3] = {1, g.nx, g.nx * g.ny};
+  const int face[3] = {cy + g.ny * cz, cx + g.nx * cz, cx + g.nx * cy};
+  double sh0 = 0.0, shn[DIM][2];  // warm-start shift of this cell and its neighbours
+  if constexpr (SHIFT) {
+    const double* __restrict__ sb = p.shift + (size_t)b * ncp;
+    sh0 = sb[Pc];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      shn[a][0] = co[a] > 0 ? sb[Pc - str[a]] : sh0;
+      shn[a][1] = co[a] < ext[a] - 1 ? sb[Pc + str[a]] : sh0;
+    }
+  }
+
+  CompSum S;
+  double Splain = 0.0, num = 0.0, den = 0.0;
+  for (int d = 0; d < g.nd; ++d) {
+    const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
+    const int fl = cld(p.t.dflags, (size_t)d);
+    const double wd = cld(p.t.w, (size_t)d);
+    const Real* __restrict__ slab = Ikb + (size_t)d * ncp;
+    const Real ik_r = buf_load_raw<Real>(slab_rsrc(slab, slab_bytes), voff);
+    const Real in_r = buf_load_raw<Real>(slab_rsrc(Inb + (size_t)d * ncp, slab_bytes), voff);
+    // Upwind value along each axis: the inflow neighbour, or on a wall face
+    // the ghost (Eq. eq-bdry) -- the isothermal wall's equilibrium, or this
+    // cell's own intensity in the mirrored direction.  Both candidates are
+    // loaded for every lane from valid addresses, before any is waited for.
+    Real nb_r[DIM];
+    double wt[DIM];
+    bool inside[DIM], iso[DIM], flows[DIM], minus[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      flows[a] = dir_pos(fl, a) || dir_neg(fl, a);
+      minus[a] = dir_pos(fl, a);  // inflow from the minus side
+      inside[a] = minus[a] ? co[a] > 0 : co[a] < ext[a] - 1;
+      const int side = 2 * a + (minus[a] ? 0 : 1);
+      iso[a] = p.t.wall[side] == 0;
+      const int r = iso[a] ? d : cld(p.t.mirror, (size_t)a * g.nd + d);
+      const Real* src = inside[a] ? slab + (minus[a] ? Pc - str[a] : Pc + str[a])
+                                  : Ikb + (size_t)r * ncp + Pc;
+      nb_r[a] = *src;
+      const double* __restrict__ wtab = iso[a] ? p.t.wall_I0[side] : p.t.w;
+      wt[a] = wtab[iso[a] ? (size_t)b * p.t.wall_nf[side] + face[a] : 0];
+    }
+    const double ik = decode(iref, ik_r) + (SHIFT ? sh0 : 0.0);
+    const double in = decode(iref, in_r);
+    double acc = (in - ik) * p.inv_dt + (I0P - ik) * inv_tau;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      if (!flows[a]) continue;
+      double up;
+      if (!inside[a] && iso[a]) {
+        up = wt[a];
+      } else {
+        up = decode(iref, nb_r[a]);
+        if constexpr (SHIFT) up += inside[a] ? shn[a][minus[a] ? 0 : 1] : sh0;
+      }
+      acc += cf.c[a] * (up - ik);
+    }
+    const Real inew_r = encode<Real>(iref, ik + acc * cf.scale);
+    if (active) buf_store<Real>(inew_r, slab_rsrc(Iob + (size_t)d * ncp, slab_bytes), voff, 0);
+    const double inew = decode(iref, inew_r);
+    const double da = inew - ik;
+    const double dn = inew - in;
+    if (active) {
+      if constexpr (Storage<Real>::kDeviation) S.add(wd * inew);
+      else Splain += wd * inew;
+      num += wd * da * da;
+      den += wd * dn * dn;
+    }
+  }
+  if (active) p.S[(size_t)b * ncp + P] = Storage<Real>::kDeviation ? S.value() : Splain;
+
+  __shared__ double red[2][kSweepBlock / 64];
+  num = wave_sum(num);
+  den = wave_sum(den);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = num;
+    red[1][wave] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int i = 0; i < kSweepBlock / 64; ++i) {
+      a += red[0][i];
+      c += red[1][i];
+    }
+    const size_t blk = (size_t)by * gx + bx;
+    p.part[2 * blk] = a;
+    p.part[2 * blk + 1] = c;
+  }
 }
+
+template <typename Real, int DIM, bool SHIFT>
+__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Real> p) {
+  if (step_done(p.ctl)) return;
+  sweep_body<Real, DIM, SHIFT>(p, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// ---------------------------------------------------------------- 2D column walk
 
 // The same update as sweep_kernel for 2D meshes, organised for reuse: a
 // workgroup owns a tile of 64 columns x (4 * RY) rows of one band and a group of
