@@ -132,7 +132,8 @@ typedef struct {
      judges the guess; an implausible guess in a cell falls back to T_n. */
   int warm_start;       /* BTE_WARM_NONE / BTE_WARM_T / BTE_WARM_T_SHIFT */
   int nn_train_steps;   /* plain steps recorded before training (<= 0: 20) */
-  int nn_epochs;        /* passes over the recorded samples (<= 0: 2) */
+  int nn_epochs;        /* passes over the recorded samples (<= 0: at least 2 passes
+                           and at least 300 minibatch updates) */
   float nn_lr;          /* Adam learning rate (<= 0: 1e-3) */
   unsigned long long nn_seed;  /* initial-weight seed (SplitMix64 counter stream) */
 } bte_options;
