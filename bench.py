@@ -133,8 +133,7 @@ def run_c5(args):
     for k, inst in enumerate(insts):
         s = bte.Solver(inst, stream=stream, precision=bte.BTE_FP32_MIXED,
                        warm_start=bte.BTE_WARM_T, nn_train_steps=20, nn_seed=inst.seed)
-        if inst.dim == 2:
-            s.autotune(cache, ry=4)
+        s.autotune(cache, ry=4) if inst.dim == 2 else s.autotune(cache, ry=2, rz=2)
         sols.append(s)
         if (k + 1) % 16 == 0:
             log(f"c5: {k + 1} contexts created")

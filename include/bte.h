@@ -216,15 +216,19 @@ int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const
                     const double* T_next, size_t n_cells, float* grad, size_t n, double* loss,
                     float* y_out);
 
-/* Sweep layout tuning.  Times the candidate layouts (rows walked per wave,
- * direction groups) of this context's shape on the device and keeps the
- * fastest, or takes the layout recorded for the same shape in the text file
- * cache_path (appended to after a measurement; NULL = no cache).  *ry is
- * in/out: 4 or 8 on entry restricts the search to that row count (batches
- * need 4), anything else searches all.  The choice is returned in *ry, *ndg
- * and its sweep time (measured now or recorded in the cache) in *sweep_ms (all
- * nullable; -1 for shapes with a single layout: 3D contexts have one). */
-int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry, int* ndg, double* sweep_ms);
+/* Sweep layout tuning.  Times the candidate layouts of this context's shape on
+ * the device and keeps the fastest, or takes the layout recorded for the same
+ * shape in the text file cache_path (appended to after a measurement; NULL =
+ * no cache).  2D layouts: 4 or 8 rows walked per wave x 1-16 direction
+ * groups; 3D layouts: 2x2, 1x4 or 2x4 (rows x planes held per wave) x 1-4
+ * direction groups.  *ry and *rz are in/out: a positive value on entry
+ * restricts the search to that row / plane count (batches need 4 rows in 2D,
+ * 2x2 in 3D).  The choice is returned in *ry, *rz, *ndg and its sweep time
+ * (measured now or recorded in the cache) in *sweep_ms (all nullable; -1 for
+ * shapes with a single layout).  BTE_E_INVAL if the restriction matches no
+ * layout. */
+int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry, int* rz, int* ndg,
+                 double* sweep_ms);
 
 /* Batched stepping of independent contexts (geometries of any size, 2D or
  * 3D, one precision, sharing one stream): every inner iteration of all of them

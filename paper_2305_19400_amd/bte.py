@@ -115,7 +115,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.bte_nn_gradient.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_size_t, _fp, C.c_size_t,
                                     _dp, _fp]
     lib.bte_destroy.argtypes = [C.c_void_p]
-    lib.bte_autotune.argtypes = [C.c_void_p, C.c_char_p, _ip, _ip, _dp]
+    lib.bte_autotune.argtypes = [C.c_void_p, C.c_char_p, _ip, _ip, _ip, _dp]
     lib.bte_batch_create.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int,
                                      C.POINTER(C.c_void_p)]
     lib.bte_batch_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(bte_step_stats)]
@@ -293,13 +293,14 @@ class Solver:
                                         y.ctypes.data_as(fp)))
         return loss.value, g, y
 
-    def autotune(self, cache_path: Optional[str] = None, ry: int = 0):
-        """Pick the fastest sweep layout for this shape (only layouts walking ``ry``
-        rows per wave if ry is 4 or 8); returns (ry, ndg, sweep ms)."""
-        ry, ndg, ms = C.c_int(int(ry)), C.c_int(0), C.c_double(0.0)
+    def autotune(self, cache_path: Optional[str] = None, ry: int = 0, rz: int = 0):
+        """Pick the fastest sweep layout for this shape (only layouts with ``ry`` rows
+        / ``rz`` planes per wave where these are positive); returns
+        (ry, rz, direction groups, sweep ms)."""
+        ry_, rz_, ndg, ms = C.c_int(int(ry)), C.c_int(int(rz)), C.c_int(0), C.c_double(0.0)
         _check(self.lib.bte_autotune(self._ctx, cache_path.encode() if cache_path else None,
-                                     C.byref(ry), C.byref(ndg), C.byref(ms)))
-        return ry.value, ndg.value, ms.value
+                                     C.byref(ry_), C.byref(rz_), C.byref(ndg), C.byref(ms)))
+        return ry_.value, rz_.value, ndg.value, ms.value
 
     def sweep_time(self):
         """(total ms, count) of sweep kernels timed since the last call."""

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/bte.h"
@@ -43,7 +44,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t ctl, coef, dflags, mirror, w, Cb, xfac, inv_tau, fweight, Iref;
-  size_t wallT[6], wallI0[6];
+  size_t wallT[6], wallI0[6], wallS[6];
   size_t T, Tprev, E, I0, S, part;
   // learned warm start (present if warm_start != 0)
   size_t nn_params, nn_grad, nn_m, nn_v, nn_W1b, nn_W2b, nn_W2Tb, nn_y, nn_hist, nn_loss,
@@ -89,6 +90,7 @@ Layout make_layout(const Shape& s) {
   for (int f = 0; f < 6; ++f) {
     L.wallT[f] = s.iso[f] ? take(sizeof(double) * (size_t)s.nf[f]) : 0;
     L.wallI0[f] = s.iso[f] ? take(sizeof(double) * (size_t)s.nf[f] * s.nb) : 0;
+    L.wallS[f] = s.iso[f] ? take(s.real_size * (size_t)s.nf[f] * s.nb) : 0;
   }
   L.T = take(sizeof(double) * (size_t)s.ncp);
   L.Tprev = take(sizeof(double) * (size_t)s.ncp);
@@ -163,19 +165,28 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   s.ncp = (int)((nc + kSlabAlign - 1) / kSlabAlign * kSlabAlign);
   s.nd = d->n;
   s.nb = b->n;
-  // Launch layout of the sweep; BTE_SWEEP_RY / BTE_SWEEP_NDG / BTE_SWEEP_KIND
-  // override the rows per wave, the number of direction groups and the kernel
-  // family (tuning knobs).
+  // Launch layout of the sweep; BTE_SWEEP_RY / BTE_SWEEP_RZ / BTE_SWEEP_NDG /
+  // BTE_SWEEP_KIND override the rows and planes per wave, the number of
+  // direction groups and the kernel family (tuning knobs).
   s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", 0),
-                           env_int("BTE_SWEEP_NDG", 0), env_int("BTE_SWEEP_KIND", -1));
+                           env_int("BTE_SWEEP_RZ", 0), env_int("BTE_SWEEP_NDG", 0),
+                           env_int("BTE_SWEEP_KIND", -1));
   s.ndg_cap = s.plan.ndg;
   s.nparts_cap = s.plan.nparts;
   if (s.plan.kind == kSweepColumnWalk2D) {
     // the 4-row layout has the most tiles; up to 16 direction groups
-    const SweepPlan widest = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 4,
+    const SweepPlan widest = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 4, 1,
                                              std::min(s.nd, 16), kSweepColumnWalk2D);
     s.ndg_cap = std::max(s.ndg_cap, widest.ndg);
     s.nparts_cap = std::max(s.nparts_cap, widest.ntiles * s.nb * s.ndg_cap);
+  } else if (s.plan.kind == kSweepColumnWalk3D) {
+    // 2 x 2 and 1 x 4 (rows x planes) have the most tiles; up to 4 direction groups
+    const SweepPlan a = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 2, 2,
+                                        std::min(s.nd, 4), kSweepColumnWalk3D);
+    const SweepPlan c = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 1, 4,
+                                        std::min(s.nd, 4), kSweepColumnWalk3D);
+    s.ndg_cap = std::max(s.ndg_cap, std::max(a.ndg, c.ndg));
+    s.nparts_cap = std::max(s.nparts_cap, std::max(a.ntiles, c.ntiles) * s.nb * s.ndg_cap);
   }
   s.real_size = o->precision == BTE_FP64 ? sizeof(double) : sizeof(float);
   s.warm = o->warm_start;
@@ -637,6 +648,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
     t.wall[f] = (f < 2 * s.dim) ? mesh->wall[f] : BTE_WALL_SPECULAR;
     t.wall_nf[f] = s.nf[f];
     t.wall_I0[f] = s.iso[f] ? at<double>(ws, L.wallI0[f]) : nullptr;
+    t.wall_S[f] = s.iso[f] ? static_cast<const void*>(ws + L.wallS[f]) : nullptr;
   }
 
   auto cleanup_fail = [&](int code) {
@@ -681,6 +693,15 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
         for (int i = 0; i < s.nf[f]; ++i) T_ref = std::min(T_ref, mesh->wall_T[f][i]);
   }
   CREATE_TRY(launch_reference(ctx->stream, nb, t.Cb, t.xfac, T_ref, at<double>(ws, L.Iref)));
+  for (int f = 0; f < 6; ++f) {
+    if (!s.iso[f]) continue;
+    if (opt->precision == BTE_FP64)
+      CREATE_TRY(launch_wall_storage<double>(ctx->stream, nb, s.nf[f], t.wall_I0[f], t.Iref,
+                                             at<double>(ws, L.wallS[f])));
+    else
+      CREATE_TRY(launch_wall_storage<float>(ctx->stream, nb, s.nf[f], t.wall_I0[f], t.Iref,
+                                            at<float>(ws, L.wallS[f])));
+  }
   ctx->Iref.assign(nb, 0.0);
   CREATE_TRY(hipMemcpyAsync(ctx->Iref.data(), at<double>(ws, L.Iref), sizeof(double) * nb,
                             hipMemcpyDeviceToHost, ctx->stream));
@@ -935,64 +956,82 @@ static void apply_plan(bte_ctx* ctx, const SweepPlan& pl) {
   ctx->g.ndg = pl.ndg;
 }
 
-int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* ndg_out,
+int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out, int* ndg_out,
                  double* ms_out) {
   if (!ctx) return fail(BTE_E_INVAL, "null context");
   if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
+  const int kind = ctx->s.plan.kind;
+  // candidate (rows, planes) per wave and direction-group counts of this kernel family
+  std::vector<std::pair<int, int>> shapes;
+  std::vector<int> groups;
+  if (kind == kSweepColumnWalk2D) {
+    shapes = {{4, 1}, {8, 1}};
+    groups = {1, 2, 4, 8, 16};
+  } else if (kind == kSweepColumnWalk3D) {
+    shapes = {{2, 2}, {1, 4}, {2, 4}};
+    groups = {1, 2, 4};
+  }
+  const int ry_only = ry_out ? *ry_out : 0;
+  const int rz_only = rz_out ? *rz_out : 0;
+  auto allowed = [&](int ry, int rz) {
+    bool listed = false;
+    for (const auto& sh : shapes) listed |= (sh.first == ry && sh.second == rz);
+    return listed && (ry_only <= 0 || ry == ry_only) && (rz_only <= 0 || rz == rz_only);
+  };
+  auto plan_for = [&](int ry, int rz, int ndg) {
+    return make_sweep_plan(ctx->s.dim, ctx->s.nx, ctx->s.ny, ctx->s.nz, ctx->s.nd, ctx->s.nb, ry,
+                           rz, ndg, kind);
+  };
+  auto fits = [&](const SweepPlan& pl) {
+    return pl.ndg <= ctx->s.ndg_cap && pl.nparts <= ctx->s.nparts_cap;
+  };
   const std::string key = tune_key(ctx);
-  const int ry_only = (ry_out && (*ry_out == 4 || *ry_out == 8)) ? *ry_out : 0;
   SweepPlan best = ctx->s.plan;
   double best_ms = -1.0;
-  bool cached = false;
-  if (cache_path) {
+  bool found = shapes.empty();  // a single-layout family needs no search
+  if (!found && cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
       char line[256];
       while (fgets(line, sizeof line, f)) {
         const char* sep = strstr(line, " -> ");
         if (!sep || std::string(line, sep - line) != key) continue;
-        int ry = 0, ndg = 0;
+        int ry = 0, rz = 0, ndg = 0;
         double ms = 0.0;
-        if (sscanf(sep + 4, "ry=%d ndg=%d ms=%lf", &ry, &ndg, &ms) == 3 &&
-            (ry_only == 0 || ry == ry_only)) {
-          const SweepPlan pl = make_sweep_plan(ctx->s.dim, ctx->s.nx, ctx->s.ny, ctx->s.nz,
-                                               ctx->s.nd, ctx->s.nb, ry, ndg, ctx->s.plan.kind);
-          if (pl.ndg <= ctx->s.ndg_cap && pl.nparts <= ctx->s.nparts_cap) {
+        if (sscanf(sep + 4, "ry=%d rz=%d ndg=%d ms=%lf", &ry, &rz, &ndg, &ms) == 4 &&
+            allowed(ry, rz)) {
+          const SweepPlan pl = plan_for(ry, rz, ndg);
+          if (fits(pl)) {
             best = pl;
             best_ms = ms;
-            cached = true;
+            found = true;
           }
         }
       }
       fclose(f);
     }
   }
-  if (!cached && ctx->s.plan.kind == kSweepColumnWalk2D) {
+  if (!found) {
     // time every candidate layout on this context's own state: sweeps write only
     // the iterate buffers and partials, so the state is untouched
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int ndgs[] = {1, 2, 4, 8, 16};
-    for (int ry : {4, 8}) {
-      if (ry_only != 0 && ry != ry_only) continue;
-      for (int nd_try : ndgs) {
-        const SweepPlan pl = make_sweep_plan(ctx->s.dim, ctx->s.nx, ctx->s.ny, ctx->s.nz,
-                                             ctx->s.nd, ctx->s.nb, ry, nd_try, kSweepColumnWalk2D);
-        if (pl.ndg != nd_try || pl.ndg > ctx->s.ndg_cap || pl.nparts > ctx->s.nparts_cap) continue;
+    for (const auto& sh : shapes) {
+      if (!allowed(sh.first, sh.second)) continue;
+      for (int nd_try : groups) {
+        const SweepPlan pl = plan_for(sh.first, sh.second, nd_try);
+        if (pl.ndg != nd_try || !fits(pl)) continue;
         apply_plan(ctx, pl);
         HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
         ctx->first_shift = nullptr;
-        int rc = ctx->opt.precision == BTE_FP64
-                     ? enqueue_sweep<double>(ctx, ctx->In, ctx->Ia, nullptr)
-                     : enqueue_sweep<float>(ctx, ctx->In, ctx->Ia, nullptr);
-        if (rc != BTE_OK) return rc;
-        HIP_TRY(hipEventRecord(e0, ctx->stream));
-        for (int r = 0; r < 3; ++r) {
+        int rc = BTE_OK;
+        for (int r = 0; r < 4 && rc == BTE_OK; ++r) {
+          if (r == 1) HIP_TRY(hipEventRecord(e0, ctx->stream));  // first launch warms up
           rc = ctx->opt.precision == BTE_FP64
                    ? enqueue_sweep<double>(ctx, ctx->In, ctx->Ia, nullptr)
                    : enqueue_sweep<float>(ctx, ctx->In, ctx->Ia, nullptr);
-          if (rc != BTE_OK) return rc;
         }
+        if (rc != BTE_OK) return rc;
         HIP_TRY(hipEventRecord(e1, ctx->stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1006,9 +1045,11 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* ndg_out
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (best_ms < 0.0) return fail(BTE_E_INVAL, "no layout matches the requested rows/planes");
     if (cache_path) {
       if (FILE* f = fopen(cache_path, "a")) {
-        fprintf(f, "%s -> ry=%d ndg=%d ms=%.6f\n", key.c_str(), best.ry, best.ndg, best_ms);
+        fprintf(f, "%s -> ry=%d rz=%d ndg=%d ms=%.6f\n", key.c_str(), best.ry, best.rz, best.ndg,
+                best_ms);
         fclose(f);
       }
     }
@@ -1017,6 +1058,7 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* ndg_out
   HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   if (ry_out) *ry_out = best.ry;
+  if (rz_out) *rz_out = best.rz;
   if (ndg_out) *ndg_out = best.ndg;
   if (ms_out) *ms_out = best_ms;
   return BTE_OK;
@@ -1085,8 +1127,11 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
       return fail(BTE_E_INVAL, "batches run the implicit scheme");
     if (c->s.warm == BTE_WARM_T_SHIFT)
       return fail(BTE_E_INVAL, "batches seed warm starts through the temperature only");
-    if (c->s.plan.kind == kSweepColumnWalk2D && c->s.plan.ry != 4)
-      return fail(BTE_E_INVAL, "batches need the 4-row sweep layout (context %d)", i);
+    const SweepPlan& pl = c->s.plan;
+    if (!(pl.kind == kSweepColumnWalk2D && pl.ry == 4) &&
+        !(pl.kind == kSweepColumnWalk3D && pl.ry == 2 && pl.rz == 2))
+      return fail(BTE_E_INVAL,
+                  "batches need the 4-row 2D or the 2x2 3D column-walk layout (context %d)", i);
     if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(BTE_E_INVAL, "context %d appears twice", i);
@@ -1113,7 +1158,7 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   for (int i : order) {
     const SweepPlan& pl = ctxs[i]->s.plan;
     auto& dst = pl.kind == kSweepColumnWalk2D ? items2 : items3;
-    const int nz = pl.kind == kSweepColumnWalk2D ? pl.ndg : 1;
+    const int nz = pl.ndg;  // direction groups
     for (int bz = 0; bz < nz; ++bz)
       for (int by = 0; by < ctxs[i]->s.nb; ++by)
         for (int bx = 0; bx < pl.ntiles; ++bx) dst.push_back(BatchItem{i, bx, by, bz});
@@ -1127,8 +1172,8 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  b->sweep_blocks[0] = cus * batch_sweep_occupancy(b->precision, true);
-  b->sweep_blocks[1] = cus * batch_sweep_occupancy(b->precision, false);
+  b->sweep_blocks[0] = cus * batch_sweep_occupancy(b->precision, kSweepColumnWalk2D);
+  b->sweep_blocks[1] = cus * batch_sweep_occupancy(b->precision, kSweepColumnWalk3D);
   int blocks = 0;
   for (int i = 0; i < n; ++i) blocks += (ctxs[i]->s.nc + 31) / 32;
   b->temp_blocks = blocks;

@@ -56,20 +56,23 @@ struct Geometry {
 };
 
 // How a sweep is laid out on the device.
-enum SweepKind { kSweepCellPerThread = 0, kSweepColumnWalk2D = 1 };
+enum SweepKind { kSweepCellPerThread = 0, kSweepColumnWalk2D = 1, kSweepColumnWalk3D = 2 };
 
 struct SweepPlan {
   int kind;
   int ry;        // rows walked per wave (column-walk kernels)
+  int rz;        // planes held per wave (3D column walk)
   int ntx, nty;  // tiles along x (64 lanes each) and along y (4 waves x ry rows each)
+  int ntz;       // tiles along z (rz planes each; 1 in 2D)
   int ndg, dgs;  // direction groups and directions per group
   int ntiles;    // workgroups per (band, direction group)
   int nparts;    // norm partials written per sweep (one per workgroup)
 };
 
-// Chooses the sweep layout for a mesh; ry / ndg <= 0 and kind < 0 pick defaults.
-SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int ndg,
-                          int kind);
+// Chooses the sweep layout for a mesh; ry / rz / ndg <= 0 and kind < 0 pick
+// defaults.
+SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int rz,
+                          int ndg, int kind);
 
 struct Tables {
   const Coef* coef;          // [nb][nd]
@@ -85,6 +88,7 @@ struct Tables {
   double W;                  // sum of the direction weights
   int wall[6];
   const double* wall_I0[6];  // [nb][nfaces] for isothermal walls, else null
+  const void* wall_S[6];     // the same in intensity storage format (Real, minus Iref)
   int wall_nf[6];
 };
 
@@ -165,13 +169,19 @@ hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* c
                                   int nctx, const BatchItem* items, int n2d, int n3d,
                                   BatchControl* bc, const int sweep_blocks[2], int temp_blocks);
 hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, BatchControl* bc);
-int batch_sweep_occupancy(int precision, bool walk2d);
+int batch_sweep_occupancy(int precision, int kind);
 
 hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* T, double* I0, double* E);
 
 hipError_t launch_wall_table(hipStream_t stream, int nb, int nf, const double* Cb,
                              const double* xfac, const double* wallT, double* out);
+
+// The isothermal wall table in intensity storage format: out[i] = in[i] - Iref[i / nf]
+// as Real (identity for FP64).
+template <typename Real>
+hipError_t launch_wall_storage(hipStream_t stream, int nb, int nf, const double* in,
+                               const double* Iref, Real* out);
 
 // Iref[b] = I0_b(T_ref) if T_ref > 0, else 0.
 hipError_t launch_reference(hipStream_t stream, int nb, const double* Cb, const double* xfac,

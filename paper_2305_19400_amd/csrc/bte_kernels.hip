@@ -538,9 +538,292 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
                                gridDim.y);
 }
 
-SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int ndg,
-                          int kind) {
+// ---------------------------------------------------------------- 3D column walk
+// The 3D counterpart of walk2d_body.  A workgroup owns 64 columns x (4 * RY)
+// rows x RZ planes of one band and a group of directions; each wave holds RY
+// rows x RZ planes of its 64 columns in registers.  The y- and z-upwind
+// neighbours inside the block come from registers, the x-upwind neighbour
+// from the adjacent lane; per direction one load per block face row fetches
+// the inflow values outside the block -- the neighbouring block, or on a wall
+// the ghost: the isothermal wall's equilibrium (kept in storage format, so it
+// is one load from a wave-uniformly chosen buffer like any slab value) or the
+// wall cell's own intensity in the mirrored direction.  Every load of a
+// direction is issued before the first wait.
+template <typename Real, int RY, int RZ, bool SHIFT>
+__device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const int ntx,
+                                            const int nty, const int dgs, const int bx,
+                                            const int by, const int bz, const int gx,
+                                            const int gy) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
+  constexpr int sz = (int)sizeof(Real);
+  const Geometry& g = p.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int tx = bx % ntx;
+  const int ty = (bx / ntx) % nty;
+  const int tz = bx / (ntx * nty);
+  const int b = by;
+  const int dg = bz;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x0 = tx * 64;
+  const int x = x0 + lane;
+  const int y0 = ty * (4 * RY) + wave * RY;
+  const int z0 = tz * RZ;
+  const int nrows = max(0, min(RY, ny - y0));
+  const int nplanes = max(0, min(RZ, nz - z0));
+  const bool live = nrows > 0 && nplanes > 0;
+  const bool colok = x < nx;
+  const int xcol = colok ? x : x0;  // a valid column for every lane
+  const int d_begin = dg * dgs;
+  const int d_end = min(g.nd, d_begin + dgs);
+  const size_t ncp = (size_t)g.ncp;
+  const size_t band_off = (size_t)b * g.nd * ncp;
+  const Real* __restrict__ Ikb = p.Ik + band_off;
+  const Real* __restrict__ Inb = p.In + band_off;
+  Real* __restrict__ Iob = p.Iout + band_off;
+  const double inv_tau = cld(p.t.inv_tau, (size_t)b);
+  const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
+  const int slab_bytes = g.nc * sz;
+  // Register cell (j, k) is row y0 + j of plane z0 + k; rows and planes past
+  // the mesh reuse the last valid one (their values are never used), so every
+  // access stays on valid cells.
+  int yr[RY], zp[RZ];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) yr[j] = min(y0 + min(j, max(nrows - 1, 0)), ny - 1);
+#pragma unroll
+  for (int k = 0; k < RZ; ++k) zp[k] = min(z0 + min(k, max(nplanes - 1, 0)), nz - 1);
+  int vc[RY][RZ];  // byte offset of this lane's cell (j, k) in a slab
+#pragma unroll
+  for (int j = 0; j < RY; ++j)
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) vc[j][k] = ((zp[k] * ny + yr[j]) * nx + xcol) * sz;
+
+  double I0r[RY][RZ], S[RY][RZ], Sc[RY][RZ], sh[RY][RZ];
+  {
+    const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        I0r[j][k] = buf_load_raw<double>(r0, vc[j][k] / sz * 8);
+        S[j][k] = 0.0;
+        Sc[j][k] = 0.0;
+        sh[j][k] = 0.0;
+        if constexpr (SHIFT) sh[j][k] = p.shift[(size_t)b * ncp + vc[j][k] / sz];
+      }
+  }
+  // Block faces.  x: lane l fetches the x-inflow value of register row
+  // (l % RY, l / RY); y: one value per plane; z: one value per row.
+  const int jl = min(lane % RY, max(nrows - 1, 0));
+  const int kl = min((lane / RY) % RZ, max(nplanes - 1, 0));
+  const int yel = min(y0 + jl, ny - 1);  // row and plane of the x edge this lane fetches
+  const int ze = min(z0 + kl, nz - 1);
+  const int last = min(63, nx - 1 - x0);   // last lane holding a mesh column
+  const bool wall_l = x0 == 0;
+  const bool wall_r = x0 + last == nx - 1;
+  const int col_l = wall_l ? 0 : x0 - 1;
+  const int col_r = wall_r ? nx - 1 : x0 + 64;
+  const bool wall_yp = y0 == 0;
+  const bool wall_yn = y0 + nrows >= ny;
+  const int row_p = wall_yp ? 0 : min(y0 - 1, ny - 1);
+  const int row_n = wall_yn ? ny - 1 : y0 + nrows;
+  const bool wall_zp = z0 == 0;
+  const bool wall_zn = z0 + nplanes >= nz;
+  const int pl_p = wall_zp ? 0 : min(z0 - 1, nz - 1);
+  const int pl_n = wall_zn ? nz - 1 : z0 + nplanes;
+  const size_t sb = (size_t)b * ncp;
+  double shx_l = 0.0, shx_r = 0.0, shy_p[RZ], shy_n[RZ], shz_p[RY], shz_n[RY];
+#pragma unroll
+  for (int k = 0; k < RZ; ++k) shy_p[k] = shy_n[k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < RY; ++j) shz_p[j] = shz_n[j] = 0.0;
+  if constexpr (SHIFT) {
+    shx_l = p.shift[sb + ((size_t)ze * ny + yel) * nx + col_l];
+    shx_r = p.shift[sb + ((size_t)ze * ny + yel) * nx + col_r];
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      shy_p[k] = p.shift[sb + ((size_t)zp[k] * ny + row_p) * nx + xcol];
+      shy_n[k] = p.shift[sb + ((size_t)zp[k] * ny + row_n) * nx + xcol];
+    }
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      shz_p[j] = p.shift[sb + ((size_t)pl_p * ny + yr[j]) * nx + xcol];
+      shz_n[j] = p.shift[sb + ((size_t)pl_n * ny + yr[j]) * nx + xcol];
+    }
+  }
+  double num = 0.0, den = 0.0;
+
+  for (int d = d_begin; d < d_end && live; ++d) {
+    const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
+    const int fl = cld(p.t.dflags, (size_t)d);
+    const double wd = cld(p.t.w, (size_t)d);
+    const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
+    const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
+    const bool zpos = dir_pos(fl, 2), zneg = dir_neg(fl, 2);
+    const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
+    const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
+    const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
+    Real rk_v[RY][RZ], rn_v[RY][RZ];
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        rk_v[j][k] = buf_load_raw<Real>(rk, vc[j][k]);
+        rn_v[j][k] = buf_load_raw<Real>(rn, vc[j][k]);
+      }
+    // x face
+    const bool wx = xpos ? wall_l : wall_r;
+    const int sx = xpos ? 0 : 1;
+    const bool isox = wx && p.t.wall[sx] == 0;
+    const int dxs = (wx && !isox) ? cld(p.t.mirror, (size_t)d) : d;
+    const auto rxs = isox ? slab_rsrc(p.t.wall_S[sx], g.nb * p.t.wall_nf[sx] * sz)
+                          : slab_rsrc(Ikb + (size_t)dxs * ncp, slab_bytes);
+    const Real ex_r = buf_load_raw<Real>(
+        rxs, isox ? (b * p.t.wall_nf[sx] + yel + ny * ze) * sz
+                  : ((ze * ny + yel) * nx + (xpos ? col_l : col_r)) * sz);
+    // y faces
+    const bool wy = ypos ? wall_yp : wall_yn;
+    const int sy = ypos ? 2 : 3;
+    const bool isoy = wy && p.t.wall[sy] == 0;
+    const int dys = (wy && !isoy) ? cld(p.t.mirror, (size_t)g.nd + d) : d;
+    const auto rys = isoy ? slab_rsrc(p.t.wall_S[sy], g.nb * p.t.wall_nf[sy] * sz)
+                          : slab_rsrc(Ikb + (size_t)dys * ncp, slab_bytes);
+    const int row = ypos ? row_p : row_n;
+    Real ey_r[RZ];
+#pragma unroll
+    for (int k = 0; k < RZ; ++k)
+      ey_r[k] = buf_load_raw<Real>(rys, isoy ? (b * p.t.wall_nf[sy] + xcol + nx * zp[k]) * sz
+                                             : ((zp[k] * ny + row) * nx + xcol) * sz);
+    // z faces
+    const bool wz = zpos ? wall_zp : wall_zn;
+    const int sz_side = zpos ? 4 : 5;
+    const bool isoz = wz && p.t.wall[sz_side] == 0;
+    const int dzs = (wz && !isoz) ? cld(p.t.mirror, (size_t)2 * g.nd + d) : d;
+    const auto rzs = isoz ? slab_rsrc(p.t.wall_S[sz_side], g.nb * p.t.wall_nf[sz_side] * sz)
+                          : slab_rsrc(Ikb + (size_t)dzs * ncp, slab_bytes);
+    const int plane = zpos ? pl_p : pl_n;
+    Real ez_r[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+      ez_r[j] = buf_load_raw<Real>(rzs, isoz ? (b * p.t.wall_nf[sz_side] + xcol + nx * yr[j]) * sz
+                                             : ((plane * ny + yr[j]) * nx + xcol) * sz);
+    // decode once everything is in flight
+    double ex = decode(iref, ex_r);
+    double ey[RZ], ez[RY];
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) ey[k] = decode(iref, ey_r[k]);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) ez[j] = decode(iref, ez_r[j]);
+    if constexpr (SHIFT) {
+      if (!isox) ex += xpos ? shx_l : shx_r;
+#pragma unroll
+      for (int k = 0; k < RZ; ++k)
+        if (!isoy) ey[k] += ypos ? shy_p[k] : shy_n[k];
+#pragma unroll
+      for (int j = 0; j < RY; ++j)
+        if (!isoz) ez[j] += zpos ? shz_p[j] : shz_n[j];
+    }
+    double ik[RY][RZ], in[RY][RZ];
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        ik[j][k] = decode(iref, rk_v[j][k]);
+        in[j][k] = decode(iref, rn_v[j][k]);
+        if constexpr (SHIFT) ik[j][k] += sh[j][k];
+      }
+    const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        const double nbr = __shfl(ik[j][k], src_lane, 64);
+        const double exjk = read_lane(ex, j + RY * k);
+        if (colok && j < nrows && k < nplanes) {
+          const double v = ik[j][k];
+          double acc = (in[j][k] - v) * p.inv_dt + (I0r[j][k] - v) * inv_tau;
+          if (xpos) {
+            const double up = lane == 0 ? exjk : nbr;
+            acc += cf.c[0] * (up - v);
+          } else if (xneg) {
+            const double up = lane == last ? exjk : nbr;
+            acc += cf.c[0] * (up - v);
+          }
+          if (ypos) {
+            const double up = (j == 0) ? ey[k] : ik[j > 0 ? j - 1 : 0][k];
+            acc += cf.c[1] * (up - v);
+          } else if (yneg) {
+            const double up = (j == nrows - 1) ? ey[k] : ik[j + 1 < RY ? j + 1 : RY - 1][k];
+            acc += cf.c[1] * (up - v);
+          }
+          if (zpos) {
+            const double up = (k == 0) ? ez[j] : ik[j][k > 0 ? k - 1 : 0];
+            acc += cf.c[2] * (up - v);
+          } else if (zneg) {
+            const double up = (k == nplanes - 1) ? ez[j] : ik[j][k + 1 < RZ ? k + 1 : RZ - 1];
+            acc += cf.c[2] * (up - v);
+          }
+          const Real inew_r = encode<Real>(iref, v + acc * cf.scale);
+          buf_store<Real>(inew_r, ro, vc[j][k], 0);
+          const double inew = decode(iref, inew_r);
+          const double da = inew - v;
+          const double dn = inew - in[j][k];
+          if constexpr (Storage<Real>::kDeviation) {
+            const double term = wd * inew;
+            const double t = S[j][k] + term;
+            Sc[j][k] += (fabs(S[j][k]) >= fabs(term)) ? ((S[j][k] - t) + term)
+                                                      : ((term - t) + S[j][k]);
+            S[j][k] = t;
+          } else {
+            S[j][k] += wd * inew;
+          }
+          num += wd * da * da;
+          den += wd * dn * dn;
+        }
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < RY; ++j)
+#pragma unroll
+    for (int k = 0; k < RZ; ++k)
+      if (colok && j < nrows && k < nplanes)
+        p.S[((size_t)dg * g.nb + b) * ncp + vc[j][k] / sz] =
+            Storage<Real>::kDeviation ? S[j][k] + Sc[j][k] : S[j][k];
+
+  __shared__ double red[2][kSweepBlock / 64];
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (lane == 0) {
+    red[0][wave] = num;
+    red[1][wave] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int i = 0; i < kSweepBlock / 64; ++i) {
+      a += red[0][i];
+      c += red[1][i];
+    }
+    const size_t blk = ((size_t)bz * gy + by) * gx + bx;
+    p.part[2 * blk] = a;
+    p.part[2 * blk + 1] = c;
+  }
+}
+
+template <typename Real, int RY, int RZ, bool SHIFT>
+__global__ __launch_bounds__(kSweepBlock) void sweep3d_walk_kernel(const SweepParams<Real> p,
+                                                                   const int ntx, const int nty,
+                                                                   const int dgs) {
+  if (step_done(p.ctl)) return;
+  walk3d_body<Real, RY, RZ, SHIFT>(p, ntx, nty, dgs, blockIdx.x, blockIdx.y, blockIdx.z,
+                                   gridDim.x, gridDim.y);
+}
+
+SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int rz,
+                          int ndg, int kind) {
   SweepPlan pl{};
+  pl.rz = 1;
+  pl.ntz = 1;
   if (dim == 2 && kind != kSweepCellPerThread) {
     pl.kind = kSweepColumnWalk2D;
     if (ry != 4 && ry != 8 && ry != 16) ry = 4;
@@ -548,6 +831,19 @@ SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int r
     pl.ntx = (nx + 63) / 64;
     pl.nty = (ny + 4 * ry - 1) / (4 * ry);
     pl.ntiles = pl.ntx * pl.nty;
+  } else if (dim == 3 && kind != kSweepCellPerThread) {
+    pl.kind = kSweepColumnWalk3D;
+    // (rows, planes) per wave: 2 x 2 (default), 1 x 4 or 2 x 4
+    if (!((ry == 2 && rz == 2) || (ry == 1 && rz == 4) || (ry == 2 && rz == 4))) {
+      ry = 2;
+      rz = 2;
+    }
+    pl.ry = ry;
+    pl.rz = rz;
+    pl.ntx = (nx + 63) / 64;
+    pl.nty = (ny + 4 * ry - 1) / (4 * ry);
+    pl.ntz = (nz + rz - 1) / rz;
+    pl.ntiles = pl.ntx * pl.nty * pl.ntz;
   } else {
     pl.kind = kSweepCellPerThread;
     pl.ry = 1;
@@ -566,7 +862,6 @@ SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int r
   pl.dgs = (nd + ndg - 1) / ndg;
   pl.ndg = (nd + pl.dgs - 1) / pl.dgs;
   pl.nparts = pl.ntiles * nb * pl.ndg;
-  (void)nz;
   return pl;
 }
 
@@ -589,6 +884,19 @@ static void launch_sweep_t(hipStream_t stream, const SweepPlan& plan, const Swee
                            stream, p, plan.ntx, plan.dgs);
         break;
     }
+    return;
+  }
+  if (plan.kind == kSweepColumnWalk3D) {
+    const dim3 grid(plan.ntiles, g.nb, plan.ndg);
+    if (plan.rz == 4 && plan.ry == 1)
+      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 1, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+                         stream, p, plan.ntx, plan.nty, plan.dgs);
+    else if (plan.rz == 4)
+      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 2, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+                         stream, p, plan.ntx, plan.nty, plan.dgs);
+    else
+      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 2, 2, SHIFT>), grid, dim3(kSweepBlock), 0,
+                         stream, p, plan.ntx, plan.nty, plan.dgs);
     return;
   }
   const dim3 grid(plan.ntiles, g.nb);
@@ -859,6 +1167,26 @@ hipError_t launch_wall_table(hipStream_t stream, int nb, int nf, const double* C
   return hipGetLastError();
 }
 
+template <typename Real>
+__global__ void wall_storage_kernel(int n, int nf, const double* __restrict__ in,
+                                    const double* __restrict__ Iref, Real* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = encode<Real>(Storage<Real>::kDeviation ? Iref[i / nf] : 0.0, in[i]);
+}
+
+template <typename Real>
+hipError_t launch_wall_storage(hipStream_t stream, int nb, int nf, const double* in,
+                               const double* Iref, Real* out) {
+  const int n = nb * nf;
+  hipLaunchKernelGGL((wall_storage_kernel<Real>), dim3((n + 255) / 256), dim3(256), 0, stream, n,
+                     nf, in, Iref, out);
+  return hipGetLastError();
+}
+template hipError_t launch_wall_storage<double>(hipStream_t, int, int, const double*,
+                                                const double*, double*);
+template hipError_t launch_wall_storage<float>(hipStream_t, int, int, const double*,
+                                               const double*, float*);
+
 // I[b][d][P] = I0[b][P] for every direction (isotropic equilibrium); padding zeroed.
 template <typename Real>
 __global__ __launch_bounds__(256) void broadcast_kernel(Geometry g, const double* __restrict__ I0,
@@ -951,15 +1279,17 @@ __device__ __forceinline__ const SweepParams<float>& batch_params<float>(const B
 // One work item of a batched sweep.  The geometry's parameters live in device
 // memory (the source / destination iterates are rewritten there after every
 // iteration), and batches seed warm starts through the temperature only (no
-// intensity shift).
-template <typename Real, bool WALK2D>
+// intensity shift).  KIND is the column-walk family: 2D with 4 rows per wave,
+// or 3D with 2 rows x 2 planes per wave.
+template <typename Real, int KIND>
 __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w) {
   const SweepParams<Real>& p = batch_params<Real>(c);
   const SweepPlan& pl = c.plan;
-  if constexpr (WALK2D)  // batches use 4 rows per wave
+  if constexpr (KIND == kSweepColumnWalk2D)
     walk2d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else
-    sweep_body<Real, 3, false>(p, w.bx, w.by, pl.ntiles);
+    walk3d_body<Real, 2, 2, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
+                                   p.g.nb);
 }
 
 // Persistent sweep: each workgroup takes work items (geometry, tile, band,
@@ -974,7 +1304,7 @@ __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w
 // makes the loop's continuation divergent: lanes other than thread 0 then
 // circle the barrier re-reading a stale item while thread 0 waits outside the
 // inner loop, and the kernel never finishes.
-template <typename Real, bool WALK2D>
+template <typename Real, int KIND>
 __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx* __restrict__ ctxs,
                                                                   const BatchItem* __restrict__ items,
                                                                   int nitems, int* next_item) {
@@ -992,7 +1322,7 @@ __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx
     w.by = __builtin_amdgcn_readfirstlane(items[it].by);
     w.bz = __builtin_amdgcn_readfirstlane(items[it].bz);
     const BatchCtx& c = ctxs[w.ctx];
-    if (!step_done(c.ctl)) batch_item<Real, WALK2D>(c, w);
+    if (!step_done(c.ctl)) batch_item<Real, KIND>(c, w);
     if (threadIdx.x == 0) item_s = atomicAdd(next_item, 1);
   }
 }
@@ -1066,11 +1396,11 @@ static void launch_batch_sweeps(hipStream_t stream, const BatchCtx* ctxs, const 
   // the 2D and 3D work lists are consumed by two persistent launches, each
   // compiled for one kernel family so neither pays the other's registers
   if (n2d > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, true>), dim3(blocks[0]), dim3(kSweepBlock), 0,
-                       stream, ctxs, items, n2d, &bc->next_item);
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kSweepColumnWalk2D>), dim3(blocks[0]),
+                       dim3(kSweepBlock), 0, stream, ctxs, items, n2d, &bc->next_item);
   if (n3d > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, false>), dim3(blocks[1]), dim3(kSweepBlock), 0,
-                       stream, ctxs, items + n2d, n3d, &bc->pad);
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kSweepColumnWalk3D>), dim3(blocks[1]),
+                       dim3(kSweepBlock), 0, stream, ctxs, items + n2d, n3d, &bc->pad);
 }
 
 hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* ctxs,
@@ -1089,19 +1419,20 @@ hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, Batc
   return hipGetLastError();
 }
 
-int batch_sweep_occupancy(int precision, bool walk2d) {
+int batch_sweep_occupancy(int precision, int kind) {
   int n = 0;
   hipError_t e;
+  const bool w2 = kind == kSweepColumnWalk2D;
   if (precision == 0)
-    e = walk2d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<double, true>,
-                                                              kSweepBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<double, false>,
-                                                              kSweepBlock, 0);
+    e = w2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &n, batch_sweep_kernel<double, kSweepColumnWalk2D>, kSweepBlock, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &n, batch_sweep_kernel<double, kSweepColumnWalk3D>, kSweepBlock, 0);
   else
-    e = walk2d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<float, true>,
-                                                              kSweepBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_sweep_kernel<float, false>,
-                                                              kSweepBlock, 0);
+    e = w2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &n, batch_sweep_kernel<float, kSweepColumnWalk2D>, kSweepBlock, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &n, batch_sweep_kernel<float, kSweepColumnWalk3D>, kSweepBlock, 0);
   if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }

@@ -133,22 +133,31 @@ def test_batch_rejects_mixed_precision(gpu):
     b.close()
 
 
-def test_autotune_picks_a_layout_and_caches_it(gpu):
+@pytest.mark.parametrize("dim", [2, 3])
+def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
     from oracle import Oracle
-    inst = I.strip_2d(64, 48, 4, 8, 10, seed=6, nsteps=2)
-    announce("autotune")
+    if dim == 2:
+        inst = I.strip_2d(64, 48, 4, 8, 10, seed=6, nsteps=2)
+        shapes = {(4, 1), (8, 1)}
+    else:
+        inst = I.gaussian_3d(20, 18, 11, 2, 8, 6, seed=6, sigma_cells=2.5,
+                             precision=I.PRECISION_FP64, nsteps=2)
+        shapes = {(2, 2), (1, 4), (2, 4)}
+    announce(f"autotune {dim}D")
     with tempfile.TemporaryDirectory() as d:
         cache = os.path.join(d, "tune.txt")
         with gpu.Solver(inst) as s:
-            ry, ndg, ms = s.autotune(cache)
-            assert ry in (4, 8) and ndg >= 1 and ms > 0
+            ry, rz, ndg, ms = s.autotune(cache)
+            assert (ry, rz) in shapes and ndg >= 1 and ms > 0
             ref = Oracle(inst)
             sched = [x["inner"] for x in ref.run(2)]
             s.step(2, fixed_inner=sched)
             T = s.temperature()
         assert np.max(np.abs(T - ref.temperature()) / ref.temperature()) <= 1e-10
         text = open(cache).read()
-        assert f"ry={ry} ndg={ndg}" in text
+        assert f"ry={ry} rz={rz} ndg={ndg}" in text
         with gpu.Solver(inst) as s2:
-            assert s2.autotune(cache)[:2] == (ry, ndg)  # read back from the cache
+            assert s2.autotune(cache)[:3] == (ry, rz, ndg)  # read back from the cache
+            with pytest.raises(gpu.BteError):
+                s2.autotune(None, ry=3)  # no such layout
         assert open(cache).read() == text
