@@ -1011,8 +1011,10 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
     }
   }
   if (!found) {
-    // time every candidate layout on this context's own state: sweeps write only
-    // the iterate buffers and partials, so the state is untouched
+    // Time every candidate layout on this context's own state: the sweeps read
+    // one ping-pong iterate and I^n and write the other iterate and the
+    // partials, so the state is untouched.  The iterate read must not be I^n
+    // itself, or half of the reads would hit in cache and flatter every layout.
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1028,8 +1030,8 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
         for (int r = 0; r < 4 && rc == BTE_OK; ++r) {
           if (r == 1) HIP_TRY(hipEventRecord(e0, ctx->stream));  // first launch warms up
           rc = ctx->opt.precision == BTE_FP64
-                   ? enqueue_sweep<double>(ctx, ctx->In, ctx->Ia, nullptr)
-                   : enqueue_sweep<float>(ctx, ctx->In, ctx->Ia, nullptr);
+                   ? enqueue_sweep<double>(ctx, ctx->Ib, ctx->Ia, nullptr)
+                   : enqueue_sweep<float>(ctx, ctx->Ib, ctx->Ia, nullptr);
         }
         if (rc != BTE_OK) return rc;
         HIP_TRY(hipEventRecord(e1, ctx->stream));

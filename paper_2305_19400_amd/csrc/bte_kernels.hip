@@ -433,7 +433,8 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     // cell in the mirrored direction -- and the isothermal wall's equilibrium,
     // read from a valid placeholder address when the side is not isothermal),
     // and wave-uniform selects pick one after every load of this direction has
-    // been issued.
+    // been issued.  (One load from a wave-uniformly chosen buffer, as in the 3D
+    // walk, measured slower here: it left waits between the stores.)
     const bool wx = xpos ? wall_l : wall_r;  // x inflow through a wall
     const int sx = xpos ? 0 : 1;
     const bool iso_x = wx && p.t.wall[sx] == 0;
