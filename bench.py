@@ -276,30 +276,33 @@ def main():
         "T_max_K": float(T.max()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep2d_walk_kernel" if inst.dim == 2 else "sweep_kernel",
+                     "kernel": "sweep2d_walk_kernel" if inst.dim == 2 else "sweep3d_walk_kernel",
                      "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
     }
-    if prec == bte.BTE_FP64 and args.workload == "c2":
+    counters = {"c2": "sweep2d_c2_fp64_counters.json", "c3": "sweep3d_c3_fp64_counters.json"}
+    if prec == bte.BTE_FP64 and args.workload in counters:
         out["roofline"]["traffic"] = measured_traffic(
             os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
-            os.path.join(ROOT, "profiles", "sweep2d_c2_fp64_counters.json"))
-    if prec == bte.BTE_FP64 and not args.no_tts:
+            os.path.join(ROOT, "profiles", counters[args.workload]))
+    if not args.no_tts and args.steps > 20:
         # Same workload and tolerance in FP32 storage with the learned warm
         # start (trained on the first 20 steps): time to solution and the
-        # temperature error against this FP64 run.
+        # temperature error against the timed run (plain FP64, or plain FP32
+        # where FP64 does not fit in HBM).
+        base = "fp64_plain" if prec == bte.BTE_FP64 else "fp32_plain"
         warm = bte.BTE_WARM_T_SHIFT
         r = run_solo(bte, inst, bte.BTE_FP32_MIXED, args.steps, "fp32+nn", warm_start=warm,
                      nn_train_steps=20, nn_seed=1)
         k32 = sum(x["inner"] for x in r["stats"])
         trained = [x["nn_loss"] for x in r["stats"] if x["trained"]]
         out["time_to_solution"] = {
-            "fp64_plain_s": wall, "fp32_nn_s": r["wall"], "speedup": wall / r["wall"],
-            "fp64_inner_sweeps": sweeps, "fp32_nn_inner_sweeps": k32,
+            f"{base}_s": wall, "fp32_nn_s": r["wall"], "speedup": wall / r["wall"],
+            f"{base}_inner_sweeps": sweeps, "fp32_nn_inner_sweeps": k32,
             "inner_sweeps_after_training": {
-                "fp64_plain": sum(x["inner"] for x in stats[20:]),
+                base: sum(x["inner"] for x in stats[20:]),
                 "fp32_nn": sum(x["inner"] for x in r["stats"][20:])},
-            "T_max_rel_err_fp32_nn_vs_fp64": max_rel(r["T"], T), "T_rel_target": 1e-4,
+            f"T_max_rel_err_fp32_nn_vs_{base}": max_rel(r["T"], T), "T_rel_target": 1e-4,
             "nn": {"inputs": "3^dim patch x (T_n, T_n-1, E_n)", "hidden": [128, 128],
                    "train_steps": 20, "loss": trained[0] if trained else None,
                    "warm_start": "T guess + intensity shift"},

@@ -210,7 +210,8 @@ class Solver:
         _check(self.lib.bte_workspace_size(C.byref(inp.mesh), C.byref(inp.dirs),
                                            C.byref(inp.bands), C.byref(inp.opt),
                                            C.byref(nbytes)))
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._ws_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self._ws_bytes, dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:
             raise BteError(BTE_E_INVAL, "torch workspace is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -223,7 +224,7 @@ class Solver:
 
     @property
     def workspace_bytes(self) -> int:
-        return int(self.workspace.numel())
+        return self._ws_bytes
 
     def step(self, nsteps: int = 1, fixed_inner: Optional[List[int]] = None) -> List[dict]:
         st = (bte_step_stats * max(nsteps, 1))()
@@ -310,9 +311,12 @@ class Solver:
         return ms.value, n.value
 
     def close(self):
+        """Destroys the context (it synchronises its stream) and releases the
+        workspace tensor, so the memory can serve the next context at once."""
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self.lib.bte_destroy(self._ctx)
             self._ctx = C.c_void_p(0)
+        self.workspace = None
 
     def __del__(self):
         try:
