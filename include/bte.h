@@ -136,6 +136,11 @@ typedef struct {
                            and at least 300 minibatch updates) */
   float nn_lr;          /* Adam learning rate (<= 0: 1e-3) */
   unsigned long long nn_seed;  /* initial-weight seed (SplitMix64 counter stream) */
+  int nn_guard;         /* the plain iteration judges the guess: whenever nn_guard
+                           consecutive warm-started steps take more inner sweeps in
+                           total than the last nn_guard plain steps recorded before
+                           training, the guess is switched off for the rest of the run
+                           (0: 4; < 0: never) */
 } bte_options;
 
 /* Warm-start modes.  T: the first sweep of a step uses I0 at the guessed

@@ -64,7 +64,7 @@ class bte_options(C.Structure):
                 ("fail_on_notconv", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("warm_start", C.c_int), ("nn_train_steps", C.c_int), ("nn_epochs", C.c_int),
-                ("nn_lr", C.c_float), ("nn_seed", C.c_ulonglong)]
+                ("nn_lr", C.c_float), ("nn_seed", C.c_ulonglong), ("nn_guard", C.c_int)]
 
 
 class bte_step_stats(C.Structure):
@@ -173,6 +173,7 @@ class _Inputs:
         o.nn_epochs = int(opts.get("nn_epochs", 0))
         o.nn_lr = float(opts.get("nn_lr", 0.0))
         o.nn_seed = int(opts.get("nn_seed", 0))
+        o.nn_guard = int(opts.get("nn_guard", 0))
         self.mesh, self.dirs, self.bands, self.disp, self.opt = m, d, b, disp, o
 
 

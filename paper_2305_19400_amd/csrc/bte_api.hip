@@ -242,6 +242,9 @@ struct bte_ctx {
   double* nn_guess;
   int nn_nrec;      // steps recorded so far
   int nn_ready;     // network trained (or parameters set)
+  int nn_off;       // guess switched off: it did not save sweeps
+  int nn_warm_steps, nn_warm_sweeps;  // warm-started steps so far and their sweeps
+  std::vector<int> nn_plain_sweeps;   // sweeps of the recorded plain steps
   int nn_adam_t;    // Adam steps taken
   bool poisoned;
 };
@@ -374,7 +377,7 @@ int step_begin(bte_ctx* ctx, int fixed, StepState* ss) {
   ss->fixed = fixed;
   ss->limit = ss->explicit_mode ? 1 : (fixed > 0 ? fixed : ctx->opt.max_inner);
   ss->check = !ss->explicit_mode && fixed <= 0;
-  ss->warm = ctx->s.warm && ctx->nn_ready;
+  ss->warm = ctx->s.warm && ctx->nn_ready && !ctx->nn_off;
   ss->record = ctx->s.warm && !ctx->nn_ready && ctx->nn_nrec < ctx->s.nn_rec;
   ss->slot = ctx->s.warm ? ctx->nnB.hist + (size_t)ctx->nn_nrec * 4 * nc : nullptr;
   if (ss->record) HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, ss->slot, 0));
@@ -426,11 +429,28 @@ int step_finish(bte_ctx* ctx, const StepState& ss, const Control& fin, bte_step_
   }
   if (ss.record) {
     HIP_TRY(nn_record(ctx->stream, nc, ctx->T, ctx->Tprev, ctx->E, ss.slot, 1));
+    ctx->nn_plain_sweeps.push_back(fin.k);
     ctx->nn_nrec += 1;
     if (ctx->nn_nrec == ctx->s.nn_rec) {
       int rc = nn_train(ctx, &loss);
       if (rc != BTE_OK) return rc;
       trained = 1;
+    }
+  }
+  if (ss.warm) {
+    // The plain iteration judges the guess: every `guard` warm steps, their
+    // sweeps are compared with the last `guard` plain steps recorded before
+    // training, and a guess that costs sweeps is switched off for good.
+    const int guard = ctx->opt.nn_guard == 0 ? 4 : ctx->opt.nn_guard;
+    ctx->nn_warm_steps += 1;
+    ctx->nn_warm_sweeps += fin.k;
+    const int nplain = (int)ctx->nn_plain_sweeps.size();
+    if (guard > 0 && ctx->nn_warm_steps == guard && nplain >= guard) {
+      int plain = 0;
+      for (int i = nplain - guard; i < nplain; ++i) plain += ctx->nn_plain_sweeps[i];
+      if (ctx->nn_warm_sweeps > plain) ctx->nn_off = 1;
+      ctx->nn_warm_steps = 0;  // next window
+      ctx->nn_warm_sweeps = 0;
     }
   }
   if (st) {
@@ -599,6 +619,9 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   ctx->nn_guess = nullptr;
   ctx->nn_nrec = 0;
   ctx->nn_ready = 0;
+  ctx->nn_off = 0;
+  ctx->nn_warm_steps = 0;
+  ctx->nn_warm_sweeps = 0;
   ctx->nn_adam_t = 0;
   ctx->nnB = NnBuffers{};
   if (s.warm) {
@@ -869,6 +892,9 @@ int bte_nn_set_params(bte_ctx* ctx, const float* in, size_t n) {
   HIP_TRY(nn_refresh(ctx->stream, ctx->nnL, ctx->nnB));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->nn_ready = 1;
+  ctx->nn_off = 0;
+  ctx->nn_warm_steps = 0;
+  ctx->nn_warm_sweeps = 0;
   return BTE_OK;
 }
 

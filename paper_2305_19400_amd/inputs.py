@@ -350,14 +350,16 @@ def hotspot_field(n, dim, rng, peak, sigma_cells):
 
 
 def batch_geometry(rng: np.random.Generator, index: int, cells_range=(4e3, 2.6e5),
-                   dirs_range=(80, 400), freq_range=(8, 40), nsteps: int = 30) -> Instance:
+                   dirs_range=(80, 400), entries_range=(8, 40), nsteps: int = 20) -> Instance:
     """One member of the batched workload: 2D or 3D (equal odds), cell count
     log-uniform in ``cells_range`` with a random aspect ratio, a product
     direction set with N_d in ``dirs_range`` (even azimuthal count, so every wall
-    mirror maps the set onto itself), ``freq_range`` frequency bands of the
-    quadratic dispersion, one Gaussian hot spot (+10..50 K), and a random wall mix
-    (each wall isothermal at 300 K, specular or symmetry; at least one isothermal).
-    FP32 intensities, implicit steps of 1 ps to tolerance 1e-4."""
+    mirror maps the set onto itself), a number of band entries drawn directly
+    from ``entries_range`` (the longitudinal entries of the quadratic
+    dispersion over that many equal bands), one Gaussian hot spot (+10..50 K,
+    sigma 2..8 cells) and a random wall mix (each wall isothermal at a
+    temperature in [300, 320] K, specular or symmetry; at least one
+    isothermal).  FP32 intensities, implicit steps of 1 ps to tolerance 1e-4."""
     dim = int(rng.integers(2, 4))
     cells = math.exp(rng.uniform(math.log(cells_range[0]), math.log(cells_range[1])))
     if dim == 2:
@@ -373,35 +375,38 @@ def batch_geometry(rng: np.random.Generator, index: int, cells_range=(4e3, 2.6e5
     lo = 2 * math.ceil(dirs_range[0] / n_polar / 2)
     hi = 2 * math.floor(dirs_range[1] / n_polar / 2)
     n_az = int(2 * rng.integers(lo // 2, hi // 2 + 1))
-    n_freq = int(rng.integers(freq_range[0], freq_range[1] + 1))
-    bands = quadratic_bands(n_freq, rng)
+    n_entries = int(rng.integers(entries_range[0], entries_range[1] + 1))
+    full = quadratic_bands(n_entries, rng)
+    bands = {k: np.asarray(v)[:n_entries] for k, v in full.items()}  # longitudinal entries
     s, w = product_quadrature(n_polar, n_az)
     kinds = [int(rng.choice([WALL_ISOTHERMAL, WALL_SPECULAR, WALL_SYMMETRY], p=[0.5, 0.3, 0.2]))
              for _ in range(2 * dim)]
     if WALL_ISOTHERMAL not in kinds:
         kinds[int(rng.integers(0, 2 * dim))] = WALL_ISOTHERMAL
     kinds += [WALL_ISOTHERMAL] * (6 - 2 * dim)
+    wall_temps = [float(rng.uniform(300.0, 320.0)) for _ in range(6)]
     peak = rng.uniform(10.0, 50.0)
-    sigma = rng.uniform(0.1, 0.25) * min(n[:dim])
+    sigma = rng.uniform(2.0, 8.0)
     T = hotspot_field(n, dim, rng, peak, sigma)
     h = [1e-8] * dim
     return make_instance(f"c5_{index:02d}_{dim}d_" + "x".join(str(v) for v in n[:dim]) +
-                         f"_d{n_polar * n_az}_f{n_freq}", dim, n, h, kinds,
-                         uniform_walls(n, dim, kinds, [300.0] * 6), T, s, w, bands,
+                         f"_d{n_polar * n_az}_b{n_entries}", dim, n, h, kinds,
+                         uniform_walls(n, dim, kinds, wall_temps), T, s, w, bands,
                          dt=1e-12, tol=1e-4, max_inner=200, nsteps=nsteps,
                          precision=PRECISION_FP32_MIXED, seed=index)
 
 
-def config_c5(seed: int = 5, count: int = 64, cells_range=(4e3, 1.0e5),
-              nsteps: int = 30) -> List[Instance]:
+def config_c5(seed: int = 5, count: int = 64, cells_range=(4e3, 2.0e5),
+              nsteps: int = 20) -> List[Instance]:
     """Batched workload: ``count`` independent 2D/3D geometries drawn by
     ``batch_geometry`` from one seeded stream (cells log-uniform in
-    ``cells_range``, 80-400 directions, 8-40 frequency bands, hot spots and wall
-    mixes), FP32 intensities.
+    ``cells_range``, 80-400 directions, 8-40 band entries, hot spots and wall
+    mixes), FP32 intensities, 20 steps.
 
-    The default cell range is the reduced draw: with cells up to 2.6e5 the 64
-    geometries hold 3.2e10 DOF (381 GB for three FP32 intensity fields), more
-    than one GPU's 288 GB; up to 1.0e5 they hold 1.55e10 DOF (186 GB)."""
+    The default cell range is a reduced draw: with cells up to 2.6e5 the 64
+    geometries hold 2.19e10 DOF, 263 GB for three FP32 intensity fields, which
+    leaves too little of one GPU's 288 GB; up to 2.0e5 they hold 1.79e10 DOF
+    (215 GB)."""
     rng = np.random.default_rng(seed)
     return [batch_geometry(rng, i, cells_range=cells_range, nsteps=nsteps) for i in range(count)]
 

@@ -158,3 +158,30 @@ def test_training_is_deterministic(gpu):
             sol.step(4)
             out.append((sol.nn_params(), sol.temperature()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_guard_switches_off_a_guess_that_costs_sweeps(gpu):
+    """A plausible but wrong network (every guess 5 s_D off) costs sweeps; after
+    nn_guard warm steps the plain iteration's verdict switches the guess off."""
+    from oracle import mlp
+    inst = I.gaussian_3d(16, 16, 16, 4, 8, 8, seed=4, sigma_cells=3.0,
+                         precision=I.PRECISION_FP64, nsteps=16)
+    announce("guard against a harmful guess")
+    with gpu.Solver(inst, warm_start=gpu.BTE_WARM_T_SHIFT, nn_train_steps=4, nn_seed=1,
+                    nn_guard=4) as sol:
+        st = sol.step(4)  # plain steps, recorded; trained after the 4th
+        assert st[3]["trained"] == 1
+        p = mlp.random_params(3, seed=1)
+        p["w3"][:] = 0.0
+        p["b3"][:] = 5.0  # y = 5: guess T_n + 5 s_D everywhere
+        vec = sol.nn_params().copy()
+        _, norm = mlp.unpack(vec, 3)
+        sol.nn_set_params(mlp.pack(p, norm))
+        st2 = sol.step(8)
+    plain = sum(s["inner"] for s in st[:4])
+    warm = sum(s["inner"] for s in st2[:4])
+    print(f"plain {plain} warm {warm}; warm flags {[s['warm'] for s in st2]}", flush=True)
+    assert all(s["warm"] == 1 for s in st2[:4])
+    assert warm > plain
+    assert all(s["warm"] == 0 for s in st2[4:])
+    assert all(s["converged"] for s in st2)
