@@ -413,21 +413,35 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     shy_n = sb[row_n * nx + xcol];
   }
 
+  // With FP32 storage the slab rows of direction d + 1 are requested (after
+  // direction d's edge loads) before direction d is computed, so they stay in
+  // flight during the arithmetic (measured 5 % faster); with FP64 storage this
+  // measured neutral and each direction loads its own rows.
+  constexpr bool kPrefetch = Storage<Real>::kDeviation;
+  Real rk_v[RY], rn_v[RY];
+  auto load_rows = [](const Real* slab_k, const Real* slab_n, int bytes, const int (&vr)[RY],
+                      Real (&k)[RY], Real (&n)[RY]) {
+    const auto rk = slab_rsrc(slab_k, bytes);
+    const auto rn = slab_rsrc(slab_n, bytes);
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      k[j] = buf_load_raw<Real>(rk, vr[j]);
+      n[j] = buf_load_raw<Real>(rn, vr[j]);
+    }
+  };
+  if constexpr (kPrefetch)
+    if (nrows > 0 && d_begin < d_end)
+      load_rows(Ikb + (size_t)d_begin * ncp, Inb + (size_t)d_begin * ncp, slab_bytes, vrow, rk_v,
+                rn_v);
   for (int d = d_begin; d < d_end && nrows > 0; ++d) {
     const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
     const int fl = cld(p.t.dflags, d);
     const double wd = cld(p.t.w, d);
     const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
     const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
-    const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
-    const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
     const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
-    Real rk_v[RY], rn_v[RY];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      rk_v[j] = buf_load_raw<Real>(rk, vrow[j]);
-      rn_v[j] = buf_load_raw<Real>(rn, vrow[j]);
-    }
+    if constexpr (!kPrefetch)
+      load_rows(Ikb + (size_t)d * ncp, Inb + (size_t)d * ncp, slab_bytes, vrow, rk_v, rn_v);
     // Edges: both candidate sources are loaded without branching (the slab
     // value -- neighbouring tile or, through a specular/symmetry wall, the wall
     // cell in the mirrored direction -- and the isothermal wall's equilibrium,
@@ -451,6 +465,11 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
                                          ((ypos ? row_p : row_n) * nx + xcol) * (int)sizeof(Real));
     const double* __restrict__ wby = iso_y ? p.t.wall_I0[sy] : p.t.w;
     const double ey_w = wby[iso_y ? (size_t)b * p.t.wall_nf[sy] + xcol : 0];
+    Real nk_v[RY], nn_v[RY];  // direction d + 1 (clamped: the group's last re-reads d)
+    if constexpr (kPrefetch) {
+      const int dn = min(d + 1, d_end - 1);
+      load_rows(Ikb + (size_t)dn * ncp, Inb + (size_t)dn * ncp, slab_bytes, vrow, nk_v, nn_v);
+    }
     double ex = iso_x ? ex_w : decode(iref, ex_r);
     double ey = iso_y ? ey_w : decode(iref, ey_r);
     if constexpr (SHIFT) {
@@ -502,6 +521,13 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
         }
         num += wd * da * da;
         den += wd * dn * dn;
+      }
+    }
+    if constexpr (kPrefetch) {
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        rk_v[j] = nk_v[j];
+        rn_v[j] = nn_v[j];
       }
     }
   }
@@ -654,6 +680,28 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
   }
   double num = 0.0, den = 0.0;
 
+  // With FP64 storage the slab values of direction d + 1 are requested (after
+  // direction d's face loads) before direction d is computed (measured ~3 %
+  // faster); with FP32 storage this measured slower, and each direction loads
+  // its own values.
+  constexpr bool kPrefetch = !Storage<Real>::kDeviation;
+  Real rk_v[RY][RZ], rn_v[RY][RZ];
+  auto load_block = [](const Real* slab_k, const Real* slab_n, int bytes,
+                       const int (&off)[RY][RZ], Real (&k)[RY][RZ], Real (&n)[RY][RZ]) {
+    const auto rk = slab_rsrc(slab_k, bytes);
+    const auto rn = slab_rsrc(slab_n, bytes);
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+      for (int q = 0; q < RZ; ++q) {
+        k[j][q] = buf_load_raw<Real>(rk, off[j][q]);
+        n[j][q] = buf_load_raw<Real>(rn, off[j][q]);
+      }
+  };
+  if constexpr (kPrefetch)
+    if (live && d_begin < d_end)
+      load_block(Ikb + (size_t)d_begin * ncp, Inb + (size_t)d_begin * ncp, slab_bytes, vc, rk_v,
+                 rn_v);
   for (int d = d_begin; d < d_end && live; ++d) {
     const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
     const int fl = cld(p.t.dflags, (size_t)d);
@@ -661,17 +709,9 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
     const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
     const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
     const bool zpos = dir_pos(fl, 2), zneg = dir_neg(fl, 2);
-    const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
-    const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
     const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
-    Real rk_v[RY][RZ], rn_v[RY][RZ];
-#pragma unroll
-    for (int j = 0; j < RY; ++j)
-#pragma unroll
-      for (int k = 0; k < RZ; ++k) {
-        rk_v[j][k] = buf_load_raw<Real>(rk, vc[j][k]);
-        rn_v[j][k] = buf_load_raw<Real>(rn, vc[j][k]);
-      }
+    if constexpr (!kPrefetch)
+      load_block(Ikb + (size_t)d * ncp, Inb + (size_t)d * ncp, slab_bytes, vc, rk_v, rn_v);
     // x face
     const bool wx = xpos ? wall_l : wall_r;
     const int sx = xpos ? 0 : 1;
@@ -708,6 +748,11 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
     for (int j = 0; j < RY; ++j)
       ez_r[j] = buf_load_raw<Real>(rzs, isoz ? (b * p.t.wall_nf[sz_side] + xcol + nx * yr[j]) * sz
                                              : ((plane * ny + yr[j]) * nx + xcol) * sz);
+    Real nk_v[RY][RZ], nn_v[RY][RZ];  // direction d + 1 (clamped)
+    if constexpr (kPrefetch) {
+      const int dn = min(d + 1, d_end - 1);
+      load_block(Ikb + (size_t)dn * ncp, Inb + (size_t)dn * ncp, slab_bytes, vc, nk_v, nn_v);
+    }
     // decode once everything is in flight
     double ex = decode(iref, ex_r);
     double ey[RZ], ez[RY];
@@ -782,6 +827,15 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
           den += wd * dn * dn;
         }
       }
+    if constexpr (kPrefetch) {
+#pragma unroll
+      for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int k = 0; k < RZ; ++k) {
+          rk_v[j][k] = nk_v[j][k];
+          rn_v[j][k] = nn_v[j][k];
+        }
+    }
   }
 #pragma unroll
   for (int j = 0; j < RY; ++j)
