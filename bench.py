@@ -200,7 +200,7 @@ def run_c5(args):
     for k, inst in enumerate(insts):
         s = bte.Solver(inst, stream=stream, precision=bte.BTE_FP32_MIXED,
                        warm_start=bte.BTE_WARM_T, nn_train_steps=train, nn_seed=inst.seed)
-        s.autotune(cache, ry=4) if inst.dim == 2 else s.autotune(cache, ry=2, rz=2)
+        s.autotune(cache, batch=True)
         sols.append(s)
         if (k + 1) % 16 == 0:
             log(f"c5: {k + 1} contexts created")
@@ -274,7 +274,9 @@ def main():
                     help="time steps (default 200; 30 for c5)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="fp64 (default) or fp32 storage; c4 defaults to fp32, since its "
+                         "FP64 state does not fit in one GPU's memory")
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2 (default, the benchmarked 2D case), the 3D cases, or the batch")
     ap.add_argument("--no-tts", action="store_true",
@@ -294,6 +296,8 @@ def main():
         return
     if args.steps is None:
         args.steps = 200
+    if args.precision is None:
+        args.precision = "fp32" if args.workload == "c4" else "fp64"
 
     import torch
     from paper_2305_19400_amd import bte, inputs

@@ -295,10 +295,12 @@ class Solver:
                                         y.ctypes.data_as(fp)))
         return loss.value, g, y
 
-    def autotune(self, cache_path: Optional[str] = None, ry: int = 0, rz: int = 0):
+    def autotune(self, cache_path: Optional[str] = None, ry: int = 0, rz: int = 0,
+                 batch: bool = False):
         """Pick the fastest sweep layout for this shape (only layouts with ``ry`` rows
-        / ``rz`` planes per wave where these are positive); returns
-        (ry, rz, direction groups, sweep ms)."""
+        / ``rz`` planes per wave where these are positive; only layouts a batch
+        accepts with ``batch``); returns (ry, rz, direction groups, sweep ms)."""
+        ry = -1 if batch else ry
         ry_, rz_, ndg, ms = C.c_int(int(ry)), C.c_int(int(rz)), C.c_int(0), C.c_double(0.0)
         _check(self.lib.bte_autotune(self._ctx, cache_path.encode() if cache_path else None,
                                      C.byref(ry_), C.byref(rz_), C.byref(ndg), C.byref(ms)))

@@ -64,6 +64,14 @@ struct Shape {
   int nn_rec;     // recorded steps before training
 };
 
+// The layouts a batched persistent sweep compiles: 4 rows per wave in 2D,
+// 2 rows x 2 planes or 1 row x 4 planes per wave in 3D.
+bool batch_layout(int kind, int ry, int rz) {
+  if (kind == kSweepColumnWalk2D) return ry == 4;
+  if (kind == kSweepColumnWalk3D) return (ry == 2 && rz == 2) || (ry == 1 && rz == 4);
+  return false;
+}
+
 int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   return (v && *v) ? atoi(v) : dflt;
@@ -167,9 +175,14 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   s.nb = b->n;
   // Launch layout of the sweep; BTE_SWEEP_RY / BTE_SWEEP_RZ / BTE_SWEEP_NDG /
   // BTE_SWEEP_KIND override the rows and planes per wave, the number of
-  // direction groups and the kernel family (tuning knobs).
-  s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", 0),
-                           env_int("BTE_SWEEP_RZ", 0), env_int("BTE_SWEEP_NDG", 0),
+  // direction groups and the kernel family (tuning knobs).  The 3D default
+  // is 2 rows x 2 planes per wave with FP64 storage and 1 row x 4 planes with
+  // FP32 storage, the faster of the two at 64^3 and 96^3 cells.
+  const bool fp32 = o->precision != BTE_FP64;
+  const int ry_dflt = (s.dim == 3 && fp32) ? 1 : 0;
+  const int rz_dflt = (s.dim == 3 && fp32) ? 4 : 0;
+  s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", ry_dflt),
+                           env_int("BTE_SWEEP_RZ", rz_dflt), env_int("BTE_SWEEP_NDG", 0),
                            env_int("BTE_SWEEP_KIND", -1));
   s.ndg_cap = s.plan.ndg;
   s.nparts_cap = s.plan.nparts;
@@ -1002,6 +1015,7 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
   auto allowed = [&](int ry, int rz) {
     bool listed = false;
     for (const auto& sh : shapes) listed |= (sh.first == ry && sh.second == rz);
+    if (ry_only == -1) return listed && batch_layout(kind, ry, rz);
     return listed && (ry_only <= 0 || ry == ry_only) && (rz_only <= 0 || rz == rz_only);
   };
   auto plan_for = [&](int ry, int rz, int ndg) {
@@ -1156,10 +1170,9 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
     if (c->s.warm == BTE_WARM_T_SHIFT)
       return fail(BTE_E_INVAL, "batches seed warm starts through the temperature only");
     const SweepPlan& pl = c->s.plan;
-    if (!(pl.kind == kSweepColumnWalk2D && pl.ry == 4) &&
-        !(pl.kind == kSweepColumnWalk3D && pl.ry == 2 && pl.rz == 2))
+    if (!batch_layout(pl.kind, pl.ry, pl.rz))
       return fail(BTE_E_INVAL,
-                  "batches need the 4-row 2D or the 2x2 3D column-walk layout (context %d)", i);
+                  "batches need the 4-row 2D or the 2x2 or 1x4 3D column-walk layout (context %d)", i);
     if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(BTE_E_INVAL, "context %d appears twice", i);

@@ -1335,13 +1335,18 @@ __device__ __forceinline__ const SweepParams<float>& batch_params<float>(const B
 // memory (the source / destination iterates are rewritten there after every
 // iteration), and batches seed warm starts through the temperature only (no
 // intensity shift).  KIND is the column-walk family: 2D with 4 rows per wave,
-// or 3D with 2 rows x 2 planes per wave.
+// or 3D with 2 rows x 2 planes or 1 row x 4 planes per wave, chosen per
+// geometry (both hold four cells per lane, so neither raises the kernel's
+// register count above the other's).
 template <typename Real, int KIND>
 __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w) {
   const SweepParams<Real>& p = batch_params<Real>(c);
   const SweepPlan& pl = c.plan;
   if constexpr (KIND == kSweepColumnWalk2D)
     walk2d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+  else if (__builtin_amdgcn_readfirstlane(pl.ry) == 1)
+    walk3d_body<Real, 1, 4, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
+                                   p.g.nb);
   else
     walk3d_body<Real, 2, 2, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
                                    p.g.nb);

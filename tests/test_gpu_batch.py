@@ -98,6 +98,42 @@ def test_batch_equals_solo_runs(gpu, use_graph, precision):
         s.close()
 
 
+@pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
+def test_batch_mixes_3d_layouts(gpu, monkeypatch, precision):
+    """3D geometries of one batch may hold 2 rows x 2 planes or 1 row x 4
+    planes per wave; each still gives its solo result bit for bit."""
+    import torch
+    insts = geometries(precision)
+    layouts = [None, (1, 4), None, (2, 2), None]
+    stream = torch.cuda.Stream()
+    announce(f"batch with 3D layouts {layouts}, precision={precision}")
+
+    def make(i):
+        if layouts[i]:
+            monkeypatch.setenv("BTE_SWEEP_RY", str(layouts[i][0]))
+            monkeypatch.setenv("BTE_SWEEP_RZ", str(layouts[i][1]))
+        else:
+            monkeypatch.delenv("BTE_SWEEP_RY", raising=False)
+            monkeypatch.delenv("BTE_SWEEP_RZ", raising=False)
+        return gpu.Solver(insts[i], stream=stream)
+
+    solos = []
+    for i in range(len(insts)):
+        with make(i) as s:
+            st = s.step(3)
+            solos.append(([x["inner"] for x in st], s.temperature(), s.intensity()))
+    sols = [make(i) for i in range(len(insts))]
+    with gpu.Batch(sols, use_graph=True) as batch:
+        st = batch.step(3)
+    ok = True
+    for i, s in enumerate(sols):
+        assert [st[k][i]["inner"] for k in range(3)] == solos[i][0]
+        ok &= same(f"geometry {i} T", s.temperature(), solos[i][1], insts[i])
+        ok &= same(f"geometry {i} I", s.intensity(), solos[i][2], insts[i])
+        s.close()
+    assert ok
+
+
 def test_batch_with_learned_warm_start(gpu):
     import torch
     insts = geometries(I.PRECISION_FP32_MIXED)[:3]
@@ -161,3 +197,6 @@ def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
             with pytest.raises(gpu.BteError):
                 s2.autotune(None, ry=3)  # no such layout
         assert open(cache).read() == text
+        with gpu.Solver(inst) as s3:  # restricted to what a batch accepts
+            ry, rz, ndg, ms = s3.autotune(None, batch=True)
+            assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4)}) and ms > 0
