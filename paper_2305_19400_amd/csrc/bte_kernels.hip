@@ -69,11 +69,28 @@ struct Storage;
 template <>
 struct Storage<double> {
   static constexpr bool kDeviation = false;
+  using Arith = double;
 };
 template <>
 struct Storage<float> {
   static constexpr bool kDeviation = true;
+  using Arith = float;
 };
+
+// Arithmetic of the column-walk sweeps.  With FP64 storage it runs on the
+// intensities in FP64.  With FP32 storage it runs in FP32 on the stored
+// deviations I - Iref_b: every term of the point-Jacobi update is a difference
+// of two intensities of one band (I^n - I, I0 - I, I_upwind - I), so Iref_b
+// cancels and the update loses nothing beyond the rounding of the stored
+// value; the energy sum (compensated) and the norms stay FP64.
+template <typename Real>
+using Arith = typename Storage<Real>::Arith;
+// Arithmetic value of an FP64 intensity (cell equilibrium, warm-start shift).
+template <typename Real>
+__device__ __forceinline__ Arith<Real> to_arith(double iref, double I) {
+  if constexpr (Storage<Real>::kDeviation) return static_cast<float>(I - iref);
+  else return I;
+}
 
 // Intensity from a stored value (exact identity for FP64 storage).
 template <typename Real>
@@ -90,11 +107,35 @@ __device__ __forceinline__ Real encode(double iref, double I) {
 
 // ---------------------------------------------------------------- sweep
 
+// Energy sum over a direction group of one (band, cell): sum_d w_d I.  With
+// FP64 storage a plain FP64 sum of the intensities; with FP32 storage a
+// compensated (Neumaier) FP64 sum of the deviations w_d (I - Iref_b), to which
+// Iref_b sum_d w_d is added once at the end.
+template <typename Real>
+__device__ __forceinline__ void accumulate_energy(double& S, double& Sc, double w, double v) {
+  if constexpr (Storage<Real>::kDeviation) {
+    const double term = w * v;
+    const double t = S + term;
+    Sc += (fabs(S) >= fabs(term)) ? ((S - t) + term) : ((term - t) + S);
+    S = t;
+  } else {
+    S += w * v;
+  }
+}
+template <typename Real>
+__device__ __forceinline__ double energy_partial(double S, double Sc, double iref, double wsum) {
+  if constexpr (Storage<Real>::kDeviation) return iref * wsum + (S + Sc);
+  else return S;
+}
+
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
   const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float read_lane(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 // Raw buffer access to one (band, direction) slab: the base address and the
@@ -365,26 +406,30 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     vrow[j] = voff + rowoff[j];
   }
 
-  double I0r[RY], S[RY], Sc[RY], sh[RY];
+  using A = Arith<Real>;
+  A I0r[RY], sh[RY];
+  double S[RY], Sc[RY];
   {
     const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const auto v = __builtin_amdgcn_raw_buffer_load_b64(r0, (colok ? lane : 0) * 8,
                                                           rowoff[j] / (int)sizeof(Real) * 8, 0);
-      I0r[j] = __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]);
+      I0r[j] = to_arith<Real>(iref,
+                              __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]));
       S[j] = 0.0;
       Sc[j] = 0.0;
-      sh[j] = 0.0;
+      sh[j] = 0;
       if constexpr (SHIFT) {
         const auto r1 = slab_rsrc(p.shift + (size_t)b * ncp, g.nc * 8);
         const auto u = __builtin_amdgcn_raw_buffer_load_b64(r1, (colok ? lane : 0) * 8,
                                                             rowoff[j] / (int)sizeof(Real) * 8, 0);
-        sh[j] = __longlong_as_double(((long long)u[1] << 32) | (unsigned int)u[0]);
+        sh[j] = static_cast<A>(__longlong_as_double(((long long)u[1] << 32) | (unsigned int)u[0]));
       }
     }
   }
-  double num = 0.0, den = 0.0;
+  const A a_inv_dt = static_cast<A>(p.inv_dt), a_inv_tau = static_cast<A>(inv_tau);
+  double num = 0.0, den = 0.0, wsum = 0.0;
 
   // Tile edges.  Lane j fetches the x-inflow value of row y0 + j (the
   // neighbouring tile's column, or the wall ghost at the mesh edge); every lane
@@ -404,13 +449,13 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   const bool wall_n = y0 + nrows >= ny;         // -y-moving inflow through the +y wall
   const int row_p = wall_p ? 0 : min(y0 - 1, ny - 1);
   const int row_n = wall_n ? ny - 1 : y0 + nrows;
-  double shx_l = 0.0, shx_r = 0.0, shy_p = 0.0, shy_n = 0.0;
+  A shx_l = 0, shx_r = 0, shy_p = 0, shy_n = 0;
   if constexpr (SHIFT) {
     const double* __restrict__ sb = p.shift + (size_t)b * ncp;
-    shx_l = sb[ye * nx + col_l];
-    shx_r = sb[ye * nx + col_r];
-    shy_p = sb[row_p * nx + xcol];
-    shy_n = sb[row_n * nx + xcol];
+    shx_l = static_cast<A>(sb[ye * nx + col_l]);
+    shx_r = static_cast<A>(sb[ye * nx + col_r]);
+    shy_p = static_cast<A>(sb[row_p * nx + xcol]);
+    shy_n = static_cast<A>(sb[row_n * nx + xcol]);
   }
 
   // With FP32 storage the slab rows of direction d + 1 are requested (after
@@ -444,8 +489,9 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
       load_rows(Ikb + (size_t)d * ncp, Inb + (size_t)d * ncp, slab_bytes, vrow, rk_v, rn_v);
     // Edges: both candidate sources are loaded without branching (the slab
     // value -- neighbouring tile or, through a specular/symmetry wall, the wall
-    // cell in the mirrored direction -- and the isothermal wall's equilibrium,
-    // read from a valid placeholder address when the side is not isothermal),
+    // cell in the mirrored direction -- and the isothermal wall's equilibrium
+    // in storage format, read from a valid placeholder address when the side
+    // is not isothermal),
     // and wave-uniform selects pick one after every load of this direction has
     // been issued.  (One load from a wave-uniformly chosen buffer, as in the 3D
     // walk, measured slower here: it left waits between the stores.)
@@ -455,70 +501,67 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     const int dx_src = (wx && !iso_x) ? cld(p.t.mirror, (size_t)d) : d;
     const Real ex_r = buf_load_raw<Real>(slab_rsrc(Ikb + (size_t)dx_src * ncp, slab_bytes),
                                          (ye * nx + (xpos ? col_l : col_r)) * (int)sizeof(Real));
-    const double* __restrict__ wbx = iso_x ? p.t.wall_I0[sx] : p.t.w;  // valid either way
-    const double ex_w = wbx[iso_x ? (size_t)b * p.t.wall_nf[sx] + ye : 0];
+    const Real* __restrict__ wbx =  // valid either way
+        iso_x ? static_cast<const Real*>(p.t.wall_S[sx]) : reinterpret_cast<const Real*>(p.t.w);
+    const Real ex_w = wbx[iso_x ? (size_t)b * p.t.wall_nf[sx] + ye : 0];
     const bool wy = ypos ? wall_p : wall_n;  // y inflow through a wall
     const int sy = ypos ? 2 : 3;
     const bool iso_y = wy && p.t.wall[sy] == 0;
     const int dy_src = (wy && !iso_y) ? cld(p.t.mirror, (size_t)g.nd + d) : d;
     const Real ey_r = buf_load_raw<Real>(slab_rsrc(Ikb + (size_t)dy_src * ncp, slab_bytes),
                                          ((ypos ? row_p : row_n) * nx + xcol) * (int)sizeof(Real));
-    const double* __restrict__ wby = iso_y ? p.t.wall_I0[sy] : p.t.w;
-    const double ey_w = wby[iso_y ? (size_t)b * p.t.wall_nf[sy] + xcol : 0];
+    const Real* __restrict__ wby =
+        iso_y ? static_cast<const Real*>(p.t.wall_S[sy]) : reinterpret_cast<const Real*>(p.t.w);
+    const Real ey_w = wby[iso_y ? (size_t)b * p.t.wall_nf[sy] + xcol : 0];
     Real nk_v[RY], nn_v[RY];  // direction d + 1 (clamped: the group's last re-reads d)
     if constexpr (kPrefetch) {
       const int dn = min(d + 1, d_end - 1);
       load_rows(Ikb + (size_t)dn * ncp, Inb + (size_t)dn * ncp, slab_bytes, vrow, nk_v, nn_v);
     }
-    double ex = iso_x ? ex_w : decode(iref, ex_r);
-    double ey = iso_y ? ey_w : decode(iref, ey_r);
+    A ex = iso_x ? ex_w : ex_r;
+    A ey = iso_y ? ey_w : ey_r;
     if constexpr (SHIFT) {
       if (!iso_x) ex += xpos ? shx_l : shx_r;
       if (!iso_y) ey += ypos ? shy_p : shy_n;
     }
-    double ik[RY], in[RY];
+    A ik[RY], in[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      ik[j] = decode(iref, rk_v[j]);
-      in[j] = decode(iref, rn_v[j]);
+      ik[j] = rk_v[j];
+      in[j] = rn_v[j];
       if constexpr (SHIFT) ik[j] += sh[j];
     }
+    const A c0 = static_cast<A>(cf.c[0]), c1 = static_cast<A>(cf.c[1]);
+    const A scale = static_cast<A>(cf.scale);
+    wsum += wd;
     // lane holding the x-upwind neighbour (direction sign is wave-uniform)
     const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      const double nbr = __shfl(ik[j], src_lane, 64);
-      const double exj = read_lane(ex, j);
+      const A nbr = __shfl(ik[j], src_lane, 64);
+      const A exj = read_lane(ex, j);
       if (colok && j < nrows) {
-        const double v = ik[j];
-        double acc = (in[j] - v) * p.inv_dt + (I0r[j] - v) * inv_tau;
+        const A v = ik[j];
+        A acc = (in[j] - v) * a_inv_dt + (I0r[j] - v) * a_inv_tau;
         if (xpos) {
-          const double up = lane == 0 ? exj : nbr;
-          acc += cf.c[0] * (up - v);
+          const A up = lane == 0 ? exj : nbr;
+          acc += c0 * (up - v);
         } else if (xneg) {
-          const double up = lane == last ? exj : nbr;
-          acc += cf.c[0] * (up - v);
+          const A up = lane == last ? exj : nbr;
+          acc += c0 * (up - v);
         }
         if (ypos) {
-          const double up = (j == 0) ? ey : ik[j > 0 ? j - 1 : 0];
-          acc += cf.c[1] * (up - v);
+          const A up = (j == 0) ? ey : ik[j > 0 ? j - 1 : 0];
+          acc += c1 * (up - v);
         } else if (yneg) {
-          const double up = (j == nrows - 1) ? ey : ik[j + 1 < RY ? j + 1 : RY - 1];
-          acc += cf.c[1] * (up - v);
+          const A up = (j == nrows - 1) ? ey : ik[j + 1 < RY ? j + 1 : RY - 1];
+          acc += c1 * (up - v);
         }
-        const Real inew_r = encode<Real>(iref, v + acc * cf.scale);
-        buf_store<Real>(inew_r, ro, vrow[j], 0);
-        const double inew = decode(iref, inew_r);
-        const double da = inew - v;
-        const double dn = inew - in[j];
-        if constexpr (Storage<Real>::kDeviation) {
-          const double term = wd * inew;
-          const double t = S[j] + term;
-          Sc[j] += (fabs(S[j]) >= fabs(term)) ? ((S[j] - t) + term) : ((term - t) + S[j]);
-          S[j] = t;
-        } else {
-          S[j] += wd * inew;
-        }
+        const A inew = v + acc * scale;
+        buf_store<Real>(static_cast<Real>(inew), ro, vrow[j], 0);
+        const double da = static_cast<double>(inew - v);
+        const double dn = static_cast<double>(inew - in[j]);
+        accumulate_energy<Real>(S[j], Sc[j], wd, static_cast<double>(inew));
         num += wd * da * da;
         den += wd * dn * dn;
       }
@@ -535,7 +578,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   for (int j = 0; j < RY; ++j)
     if (colok && j < nrows)
       p.S[((size_t)dg * g.nb + b) * ncp + (size_t)(y0 + j) * nx + x] =
-          Storage<Real>::kDeviation ? S[j] + Sc[j] : S[j];
+          energy_partial<Real>(S[j], Sc[j], iref, wsum);
 
   __shared__ double red[2][kSweepBlock / 64];
   num = wave_sum(num);
@@ -625,20 +668,23 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
 #pragma unroll
     for (int k = 0; k < RZ; ++k) vc[j][k] = ((zp[k] * ny + yr[j]) * nx + xcol) * sz;
 
-  double I0r[RY][RZ], S[RY][RZ], Sc[RY][RZ], sh[RY][RZ];
+  using A = Arith<Real>;
+  A I0r[RY][RZ], sh[RY][RZ];
+  double S[RY][RZ], Sc[RY][RZ];
   {
     const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
 #pragma unroll
     for (int j = 0; j < RY; ++j)
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
-        I0r[j][k] = buf_load_raw<double>(r0, vc[j][k] / sz * 8);
+        I0r[j][k] = to_arith<Real>(iref, buf_load_raw<double>(r0, vc[j][k] / sz * 8));
         S[j][k] = 0.0;
         Sc[j][k] = 0.0;
-        sh[j][k] = 0.0;
-        if constexpr (SHIFT) sh[j][k] = p.shift[(size_t)b * ncp + vc[j][k] / sz];
+        sh[j][k] = 0;
+        if constexpr (SHIFT) sh[j][k] = static_cast<A>(p.shift[(size_t)b * ncp + vc[j][k] / sz]);
       }
   }
+  const A a_inv_dt = static_cast<A>(p.inv_dt), a_inv_tau = static_cast<A>(inv_tau);
   // Block faces.  x: lane l fetches the x-inflow value of register row
   // (l % RY, l / RY); y: one value per plane; z: one value per row.
   const int jl = min(lane % RY, max(nrows - 1, 0));
@@ -659,26 +705,26 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
   const int pl_p = wall_zp ? 0 : min(z0 - 1, nz - 1);
   const int pl_n = wall_zn ? nz - 1 : z0 + nplanes;
   const size_t sb = (size_t)b * ncp;
-  double shx_l = 0.0, shx_r = 0.0, shy_p[RZ], shy_n[RZ], shz_p[RY], shz_n[RY];
+  A shx_l = 0, shx_r = 0, shy_p[RZ], shy_n[RZ], shz_p[RY], shz_n[RY];
 #pragma unroll
-  for (int k = 0; k < RZ; ++k) shy_p[k] = shy_n[k] = 0.0;
+  for (int k = 0; k < RZ; ++k) shy_p[k] = shy_n[k] = 0;
 #pragma unroll
-  for (int j = 0; j < RY; ++j) shz_p[j] = shz_n[j] = 0.0;
+  for (int j = 0; j < RY; ++j) shz_p[j] = shz_n[j] = 0;
   if constexpr (SHIFT) {
-    shx_l = p.shift[sb + ((size_t)ze * ny + yel) * nx + col_l];
-    shx_r = p.shift[sb + ((size_t)ze * ny + yel) * nx + col_r];
+    shx_l = static_cast<A>(p.shift[sb + ((size_t)ze * ny + yel) * nx + col_l]);
+    shx_r = static_cast<A>(p.shift[sb + ((size_t)ze * ny + yel) * nx + col_r]);
 #pragma unroll
     for (int k = 0; k < RZ; ++k) {
-      shy_p[k] = p.shift[sb + ((size_t)zp[k] * ny + row_p) * nx + xcol];
-      shy_n[k] = p.shift[sb + ((size_t)zp[k] * ny + row_n) * nx + xcol];
+      shy_p[k] = static_cast<A>(p.shift[sb + ((size_t)zp[k] * ny + row_p) * nx + xcol]);
+      shy_n[k] = static_cast<A>(p.shift[sb + ((size_t)zp[k] * ny + row_n) * nx + xcol]);
     }
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-      shz_p[j] = p.shift[sb + ((size_t)pl_p * ny + yr[j]) * nx + xcol];
-      shz_n[j] = p.shift[sb + ((size_t)pl_n * ny + yr[j]) * nx + xcol];
+      shz_p[j] = static_cast<A>(p.shift[sb + ((size_t)pl_p * ny + yr[j]) * nx + xcol]);
+      shz_n[j] = static_cast<A>(p.shift[sb + ((size_t)pl_n * ny + yr[j]) * nx + xcol]);
     }
   }
-  double num = 0.0, den = 0.0;
+  double num = 0.0, den = 0.0, wsum = 0.0;
 
   // With FP64 storage the slab values of direction d + 1 are requested (after
   // direction d's face loads) before direction d is computed (measured ~3 %
@@ -753,13 +799,12 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
       const int dn = min(d + 1, d_end - 1);
       load_block(Ikb + (size_t)dn * ncp, Inb + (size_t)dn * ncp, slab_bytes, vc, nk_v, nn_v);
     }
-    // decode once everything is in flight
-    double ex = decode(iref, ex_r);
-    double ey[RZ], ez[RY];
+    A ex = ex_r;
+    A ey[RZ], ez[RY];
 #pragma unroll
-    for (int k = 0; k < RZ; ++k) ey[k] = decode(iref, ey_r[k]);
+    for (int k = 0; k < RZ; ++k) ey[k] = ey_r[k];
 #pragma unroll
-    for (int j = 0; j < RY; ++j) ez[j] = decode(iref, ez_r[j]);
+    for (int j = 0; j < RY; ++j) ez[j] = ez_r[j];
     if constexpr (SHIFT) {
       if (!isox) ex += xpos ? shx_l : shx_r;
 #pragma unroll
@@ -769,60 +814,54 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
       for (int j = 0; j < RY; ++j)
         if (!isoz) ez[j] += zpos ? shz_p[j] : shz_n[j];
     }
-    double ik[RY][RZ], in[RY][RZ];
+    A ik[RY][RZ], in[RY][RZ];
 #pragma unroll
     for (int j = 0; j < RY; ++j)
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
-        ik[j][k] = decode(iref, rk_v[j][k]);
-        in[j][k] = decode(iref, rn_v[j][k]);
+        ik[j][k] = rk_v[j][k];
+        in[j][k] = rn_v[j][k];
         if constexpr (SHIFT) ik[j][k] += sh[j][k];
       }
+    const A c0 = static_cast<A>(cf.c[0]), c1 = static_cast<A>(cf.c[1]);
+    const A c2 = static_cast<A>(cf.c[2]), scale = static_cast<A>(cf.scale);
+    wsum += wd;
     const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
 #pragma unroll
     for (int j = 0; j < RY; ++j)
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
-        const double nbr = __shfl(ik[j][k], src_lane, 64);
-        const double exjk = read_lane(ex, j + RY * k);
+        const A nbr = __shfl(ik[j][k], src_lane, 64);
+        const A exjk = read_lane(ex, j + RY * k);
         if (colok && j < nrows && k < nplanes) {
-          const double v = ik[j][k];
-          double acc = (in[j][k] - v) * p.inv_dt + (I0r[j][k] - v) * inv_tau;
+          const A v = ik[j][k];
+          A acc = (in[j][k] - v) * a_inv_dt + (I0r[j][k] - v) * a_inv_tau;
           if (xpos) {
-            const double up = lane == 0 ? exjk : nbr;
-            acc += cf.c[0] * (up - v);
+            const A up = lane == 0 ? exjk : nbr;
+            acc += c0 * (up - v);
           } else if (xneg) {
-            const double up = lane == last ? exjk : nbr;
-            acc += cf.c[0] * (up - v);
+            const A up = lane == last ? exjk : nbr;
+            acc += c0 * (up - v);
           }
           if (ypos) {
-            const double up = (j == 0) ? ey[k] : ik[j > 0 ? j - 1 : 0][k];
-            acc += cf.c[1] * (up - v);
+            const A up = (j == 0) ? ey[k] : ik[j > 0 ? j - 1 : 0][k];
+            acc += c1 * (up - v);
           } else if (yneg) {
-            const double up = (j == nrows - 1) ? ey[k] : ik[j + 1 < RY ? j + 1 : RY - 1][k];
-            acc += cf.c[1] * (up - v);
+            const A up = (j == nrows - 1) ? ey[k] : ik[j + 1 < RY ? j + 1 : RY - 1][k];
+            acc += c1 * (up - v);
           }
           if (zpos) {
-            const double up = (k == 0) ? ez[j] : ik[j][k > 0 ? k - 1 : 0];
-            acc += cf.c[2] * (up - v);
+            const A up = (k == 0) ? ez[j] : ik[j][k > 0 ? k - 1 : 0];
+            acc += c2 * (up - v);
           } else if (zneg) {
-            const double up = (k == nplanes - 1) ? ez[j] : ik[j][k + 1 < RZ ? k + 1 : RZ - 1];
-            acc += cf.c[2] * (up - v);
+            const A up = (k == nplanes - 1) ? ez[j] : ik[j][k + 1 < RZ ? k + 1 : RZ - 1];
+            acc += c2 * (up - v);
           }
-          const Real inew_r = encode<Real>(iref, v + acc * cf.scale);
-          buf_store<Real>(inew_r, ro, vc[j][k], 0);
-          const double inew = decode(iref, inew_r);
-          const double da = inew - v;
-          const double dn = inew - in[j][k];
-          if constexpr (Storage<Real>::kDeviation) {
-            const double term = wd * inew;
-            const double t = S[j][k] + term;
-            Sc[j][k] += (fabs(S[j][k]) >= fabs(term)) ? ((S[j][k] - t) + term)
-                                                      : ((term - t) + S[j][k]);
-            S[j][k] = t;
-          } else {
-            S[j][k] += wd * inew;
-          }
+          const A inew = v + acc * scale;
+          buf_store<Real>(static_cast<Real>(inew), ro, vc[j][k], 0);
+          const double da = static_cast<double>(inew - v);
+          const double dn = static_cast<double>(inew - in[j][k]);
+          accumulate_energy<Real>(S[j][k], Sc[j][k], wd, static_cast<double>(inew));
           num += wd * da * da;
           den += wd * dn * dn;
         }
@@ -843,7 +882,7 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
     for (int k = 0; k < RZ; ++k)
       if (colok && j < nrows && k < nplanes)
         p.S[((size_t)dg * g.nb + b) * ncp + vc[j][k] / sz] =
-            Storage<Real>::kDeviation ? S[j][k] + Sc[j][k] : S[j][k];
+            energy_partial<Real>(S[j][k], Sc[j][k], iref, wsum);
 
   __shared__ double red[2][kSweepBlock / 64];
   num = wave_sum(num);
