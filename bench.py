@@ -352,11 +352,15 @@ def main():
                      "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
     }
-    counters = {"c2": "sweep2d_c2_fp64_counters.json", "c3": "sweep3d_c3_fp64_counters.json"}
-    if prec == bte.BTE_FP64 and args.workload in counters:
+    # committed rocprofv3 counter summaries, by workload and storage precision
+    counters = {("c2", "fp64"): "sweep2d_c2_fp64_counters.json",
+                ("c3", "fp64"): "sweep3d_c3_fp64_counters.json",
+                ("c4", "fp32"): "sweep3d_c4_fp32_counters.json"}
+    key = (args.workload, args.precision)
+    if key in counters:
         out["roofline"]["traffic"] = measured_traffic(
             os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
-            os.path.join(ROOT, "profiles", counters[args.workload]))
+            os.path.join(ROOT, "profiles", counters[key]))
     if not args.no_tts and args.steps > 20:
         out["time_to_solution"] = time_to_solution(bte, inst, args.steps, prec)
     if not args.no_cpu_baseline and args.workload == "c2":
