@@ -64,11 +64,13 @@ struct Shape {
   int nn_rec;     // recorded steps before training
 };
 
-// The layouts a batched persistent sweep compiles: 4 rows per wave in 2D,
-// 2 rows x 2 planes or 1 row x 4 planes per wave in 3D.
+// The layouts a batched persistent sweep compiles: 4 rows per wave in 2D;
+// in 3D 2 rows x 2 planes or 1 row x 4 planes per wave, or the flattened
+// (x, y) plane with 2 planes per wave.
 bool batch_layout(int kind, int ry, int rz) {
   if (kind == kSweepColumnWalk2D) return ry == 4;
   if (kind == kSweepColumnWalk3D) return (ry == 2 && rz == 2) || (ry == 1 && rz == 4);
+  if (kind == kSweepFlat3D) return rz == 2;
   return false;
 }
 
@@ -175,15 +177,27 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   s.nb = b->n;
   // Launch layout of the sweep; BTE_SWEEP_RY / BTE_SWEEP_RZ / BTE_SWEEP_NDG /
   // BTE_SWEEP_KIND override the rows and planes per wave, the number of
-  // direction groups and the kernel family (tuning knobs).  The 3D default
-  // is 2 rows x 2 planes per wave with FP64 storage and 1 row x 4 planes with
-  // FP32 storage, the faster of the two at 64^3 and 96^3 cells.
+  // direction groups and the kernel family (tuning knobs).  3D defaults: when
+  // 64-column tiles would leave more than an eighth of the lanes idle (a
+  // narrow mesh or a ragged last tile), the flattened (x, y) plane with 2
+  // planes per wave (as fast as 4 planes there, and batches accept it);
+  // otherwise 2 rows x 2 planes per wave with FP64 storage and 1 row x 4
+  // planes with FP32 storage (the faster at 64^3 cells).
   const bool fp32 = o->precision != BTE_FP64;
-  const int ry_dflt = (s.dim == 3 && fp32) ? 1 : 0;
-  const int rz_dflt = (s.dim == 3 && fp32) ? 4 : 0;
+  int ry_dflt = 0, rz_dflt = 0, kind_dflt = -1;
+  if (s.dim == 3) {
+    const double lanes_used = (double)s.nx / (64.0 * ((s.nx + 63) / 64));
+    if (lanes_used < 0.875) {
+      kind_dflt = kSweepFlat3D;
+      rz_dflt = 2;
+    } else if (fp32) {
+      ry_dflt = 1;
+      rz_dflt = 4;
+    }
+  }
   s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", ry_dflt),
                            env_int("BTE_SWEEP_RZ", rz_dflt), env_int("BTE_SWEEP_NDG", 0),
-                           env_int("BTE_SWEEP_KIND", -1));
+                           env_int("BTE_SWEEP_KIND", kind_dflt));
   s.ndg_cap = s.plan.ndg;
   s.nparts_cap = s.plan.nparts;
   if (s.plan.kind == kSweepColumnWalk2D) {
@@ -192,14 +206,18 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
                                              std::min(s.nd, 16), kSweepColumnWalk2D);
     s.ndg_cap = std::max(s.ndg_cap, widest.ndg);
     s.nparts_cap = std::max(s.nparts_cap, widest.ntiles * s.nb * s.ndg_cap);
-  } else if (s.plan.kind == kSweepColumnWalk3D) {
-    // 2 x 2 and 1 x 4 (rows x planes) have the most tiles; up to 4 direction groups
+  } else if (s.plan.kind == kSweepColumnWalk3D || s.plan.kind == kSweepFlat3D) {
+    // 2 x 2, 1 x 4 (rows x planes) and the flattened 2-plane layout have the
+    // most tiles; up to 4 direction groups
     const SweepPlan a = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 2, 2,
                                         std::min(s.nd, 4), kSweepColumnWalk3D);
     const SweepPlan c = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 1, 4,
                                         std::min(s.nd, 4), kSweepColumnWalk3D);
-    s.ndg_cap = std::max(s.ndg_cap, std::max(a.ndg, c.ndg));
-    s.nparts_cap = std::max(s.nparts_cap, std::max(a.ntiles, c.ntiles) * s.nb * s.ndg_cap);
+    const SweepPlan fp = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, 0, 2,
+                                         std::min(s.nd, 4), kSweepFlat3D);
+    s.ndg_cap = std::max(s.ndg_cap, std::max(std::max(a.ndg, c.ndg), fp.ndg));
+    s.nparts_cap = std::max(s.nparts_cap, std::max(std::max(a.ntiles, c.ntiles), fp.ntiles) *
+                                              s.nb * s.ndg_cap);
   }
   s.real_size = o->precision == BTE_FP64 ? sizeof(double) : sizeof(float);
   s.warm = o->warm_start;
@@ -1000,27 +1018,32 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
   if (!ctx) return fail(BTE_E_INVAL, "null context");
   if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
   const int kind = ctx->s.plan.kind;
-  // candidate (rows, planes) per wave and direction-group counts of this kernel family
+  const bool family3d = kind == kSweepColumnWalk3D || kind == kSweepFlat3D;
+  // candidate (rows, planes) per wave and direction-group counts of this kernel
+  // family; in 3D, 0 rows stands for the flattened (x, y) plane
   std::vector<std::pair<int, int>> shapes;
   std::vector<int> groups;
   if (kind == kSweepColumnWalk2D) {
     shapes = {{4, 1}, {8, 1}};
     groups = {1, 2, 4, 8, 16};
-  } else if (kind == kSweepColumnWalk3D) {
-    shapes = {{2, 2}, {1, 4}, {2, 4}};
+  } else if (family3d) {
+    shapes = {{2, 2}, {1, 4}, {2, 4}, {0, 4}, {0, 2}};
     groups = {1, 2, 4};
   }
+  auto kind_of = [&](int ry) {
+    return family3d ? (ry == 0 ? kSweepFlat3D : kSweepColumnWalk3D) : kind;
+  };
   const int ry_only = ry_out ? *ry_out : 0;
   const int rz_only = rz_out ? *rz_out : 0;
   auto allowed = [&](int ry, int rz) {
     bool listed = false;
     for (const auto& sh : shapes) listed |= (sh.first == ry && sh.second == rz);
-    if (ry_only == -1) return listed && batch_layout(kind, ry, rz);
+    if (ry_only == -1) return listed && batch_layout(kind_of(ry), ry, rz);
     return listed && (ry_only <= 0 || ry == ry_only) && (rz_only <= 0 || rz == rz_only);
   };
   auto plan_for = [&](int ry, int rz, int ndg) {
     return make_sweep_plan(ctx->s.dim, ctx->s.nx, ctx->s.ny, ctx->s.nz, ctx->s.nd, ctx->s.nb, ry,
-                           rz, ndg, kind);
+                           rz, ndg, kind_of(ry));
   };
   auto fits = [&](const SweepPlan& pl) {
     return pl.ndg <= ctx->s.ndg_cap && pl.nparts <= ctx->s.nparts_cap;

@@ -56,7 +56,12 @@ struct Geometry {
 };
 
 // How a sweep is laid out on the device.
-enum SweepKind { kSweepCellPerThread = 0, kSweepColumnWalk2D = 1, kSweepColumnWalk3D = 2 };
+enum SweepKind {
+  kSweepCellPerThread = 0,
+  kSweepColumnWalk2D = 1,
+  kSweepColumnWalk3D = 2,
+  kSweepFlat3D = 3,  // 3D, lanes over the flattened (x, y) plane
+};
 
 struct SweepPlan {
   int kind;

@@ -913,6 +913,252 @@ __global__ __launch_bounds__(kSweepBlock) void sweep3d_walk_kernel(const SweepPa
                                    gridDim.x, gridDim.y);
 }
 
+// ---------------------------------------------------------------- 3D flattened walk
+// For meshes whose x extent leaves many lanes of a 64-column tile idle (a
+// narrow mesh, or a ragged last tile), the lanes of a wave take 64
+// consecutive cells f = x + nx y of the (x, y) plane instead, and the wave
+// holds RZ planes of them in registers; a workgroup covers 256 cells x RZ
+// planes.  The z-upwind neighbour comes from registers (one load per block
+// face plane), the x-upwind one from the adjacent lane (the wave's edge lane
+// from one load per plane), the y-upwind one from a load of the cells nx
+// away, which this or the previous wave has just read.  Lanes on an x or y
+// wall take the ghost (isothermal equilibrium in storage format, or the
+// cell's own intensity in the mirrored direction) from a load masked to them.
+template <typename Real, int RZ, bool SHIFT>
+__device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const int nft,
+                                            const int dgs, const int bx, const int by,
+                                            const int bz, const int gx, const int gy) {
+#pragma clang fp contract(on)  // fuse a*b+c only within one expression
+  using A = Arith<Real>;
+  constexpr int sz = (int)sizeof(Real);
+  const Geometry& g = p.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int nxy = nx * ny;
+  const int tf = bx % nft;
+  const int tz = bx / nft;
+  const int b = by;
+  const int dg = bz;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int f0 = tf * 256 + wave * 64;   // first plane cell of this wave
+  const int f = f0 + lane;
+  const bool fok = f < nxy;
+  const int fc = fok ? f : nxy - 1;      // a valid cell for every lane
+  const int x = fc % nx;
+  const int y = fc / nx;
+  const int z0 = tz * RZ;
+  const int nplanes = max(0, min(RZ, nz - z0));
+  const bool live = f0 < nxy && nplanes > 0;
+  const int d_begin = dg * dgs;
+  const int d_end = min(g.nd, d_begin + dgs);
+  const size_t ncp = (size_t)g.ncp;
+  const size_t band_off = (size_t)b * g.nd * ncp;
+  const Real* __restrict__ Ikb = p.Ik + band_off;
+  const Real* __restrict__ Inb = p.In + band_off;
+  Real* __restrict__ Iob = p.Iout + band_off;
+  const double inv_tau = cld(p.t.inv_tau, (size_t)b);
+  const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
+  const int slab_bytes = g.nc * sz;
+  // planes past the mesh reuse the last valid one (their values are never used)
+  int zp[RZ], vc[RZ];
+#pragma unroll
+  for (int k = 0; k < RZ; ++k) {
+    zp[k] = min(z0 + min(k, max(nplanes - 1, 0)), nz - 1);
+    vc[k] = (zp[k] * nxy + fc) * sz;
+  }
+  // neighbour cells in the plane (clamped to the cell itself on a wall)
+  const int fy_p = y > 0 ? fc - nx : fc;
+  const int fy_n = y < ny - 1 ? fc + nx : fc;
+  // the wave's x edge: lane k loads plane k's cell before f0 / after f0 + 63
+  const int kl = min(lane, RZ - 1);
+  const int fe_p = max(f0 - 1, 0);
+  const int fe_n = min(f0 + 64, nxy - 1);
+  // z block faces
+  const bool wall_zp = z0 == 0;
+  const bool wall_zn = z0 + nplanes >= nz;
+  const int pl_p = wall_zp ? 0 : z0 - 1;
+  const int pl_n = wall_zn ? nz - 1 : z0 + nplanes;
+
+  A I0r[RZ], sh[RZ];
+  double S[RZ], Sc[RZ];
+  A shy_p[RZ], shy_n[RZ];
+  A shx_p = 0, shx_n = 0, shz_p = 0, shz_n = 0;
+  {
+    const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      I0r[k] = to_arith<Real>(iref, buf_load_raw<double>(r0, vc[k] / sz * 8));
+      S[k] = 0.0;
+      Sc[k] = 0.0;
+      sh[k] = 0;
+      shy_p[k] = 0;
+      shy_n[k] = 0;
+    }
+  }
+  if constexpr (SHIFT) {
+    const double* __restrict__ sb = p.shift + (size_t)b * ncp;
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      sh[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fc]);
+      shy_p[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fy_p]);
+      shy_n[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fy_n]);
+    }
+    shx_p = static_cast<A>(sb[(size_t)zp[kl] * nxy + fe_p]);
+    shx_n = static_cast<A>(sb[(size_t)zp[kl] * nxy + fe_n]);
+    shz_p = static_cast<A>(sb[(size_t)pl_p * nxy + fc]);
+    shz_n = static_cast<A>(sb[(size_t)pl_n * nxy + fc]);
+  }
+  const A a_inv_dt = static_cast<A>(p.inv_dt), a_inv_tau = static_cast<A>(inv_tau);
+  double num = 0.0, den = 0.0, wsum = 0.0;
+
+  for (int d = d_begin; d < d_end && live; ++d) {
+    const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
+    const int fl = cld(p.t.dflags, (size_t)d);
+    const double wd = cld(p.t.w, (size_t)d);
+    const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
+    const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
+    const bool zpos = dir_pos(fl, 2), zneg = dir_neg(fl, 2);
+    const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
+    const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
+    const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
+    Real rk_v[RZ], rn_v[RZ], ey_r[RZ];
+    const int fy = ypos ? fy_p : fy_n;
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      rk_v[k] = buf_load_raw<Real>(rk, vc[k]);
+      rn_v[k] = buf_load_raw<Real>(rn, vc[k]);
+      ey_r[k] = buf_load_raw<Real>(rk, (zp[k] * nxy + fy) * sz);
+    }
+    const Real ex_r = buf_load_raw<Real>(rk, (zp[kl] * nxy + (xpos ? fe_p : fe_n)) * sz);
+    // z face: the neighbouring block's plane, or on a wall (wave-uniform) the
+    // isothermal equilibrium or this plane's cell in the mirrored direction
+    const bool wz = zpos ? wall_zp : wall_zn;
+    const int fz = zpos ? 4 : 5;
+    const bool isoz = wz && p.t.wall[fz] == 0;
+    const int dzs = (wz && !isoz) ? cld(p.t.mirror, (size_t)2 * g.nd + d) : d;
+    const auto rzs = isoz ? slab_rsrc(p.t.wall_S[fz], g.nb * p.t.wall_nf[fz] * sz)
+                          : slab_rsrc(Ikb + (size_t)dzs * ncp, slab_bytes);
+    const Real ez_r = buf_load_raw<Real>(
+        rzs, isoz ? (b * p.t.wall_nf[fz] + fc) * sz
+                  : ((zpos ? pl_p : pl_n) * nxy + fc) * sz);
+    // x and y walls: lanes on a wall load their ghosts (masked to them)
+    const bool xw = (xpos && x == 0) || (xneg && x == nx - 1);
+    const bool yw = (ypos && y == 0) || (yneg && y == ny - 1);
+    Real xg_r[RZ], yg_r[RZ];
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) xg_r[k] = yg_r[k] = 0;
+    if (xw) {
+      const int fx = xpos ? 0 : 1;
+      const bool iso = p.t.wall[fx] == 0;
+      const auto r = iso ? slab_rsrc(p.t.wall_S[fx], g.nb * p.t.wall_nf[fx] * sz)
+                         : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)d) * ncp, slab_bytes);
+#pragma unroll
+      for (int k = 0; k < RZ; ++k)
+        xg_r[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fx] + y + ny * zp[k]) * sz : vc[k]);
+      if constexpr (SHIFT)
+        if (!iso)
+#pragma unroll
+          for (int k = 0; k < RZ; ++k) xg_r[k] = static_cast<Real>(xg_r[k] + sh[k]);
+    }
+    if (yw) {
+      const int fyw = ypos ? 2 : 3;
+      const bool iso = p.t.wall[fyw] == 0;
+      const auto r = iso ? slab_rsrc(p.t.wall_S[fyw], g.nb * p.t.wall_nf[fyw] * sz)
+                         : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)g.nd + d) * ncp,
+                                     slab_bytes);
+#pragma unroll
+      for (int k = 0; k < RZ; ++k)
+        yg_r[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fyw] + x + nx * zp[k]) * sz : vc[k]);
+      if constexpr (SHIFT)
+        if (!iso)
+#pragma unroll
+          for (int k = 0; k < RZ; ++k) yg_r[k] = static_cast<Real>(yg_r[k] + sh[k]);
+    }
+    A ex = ex_r, ez = ez_r;
+    if constexpr (SHIFT) {
+      ex += xpos ? shx_p : shx_n;
+      if (!isoz) ez += zpos ? shz_p : shz_n;
+    }
+    A ik[RZ], in[RZ];
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      ik[k] = rk_v[k];
+      in[k] = rn_v[k];
+      if constexpr (SHIFT) ik[k] += sh[k];
+    }
+    const A c0 = static_cast<A>(cf.c[0]), c1 = static_cast<A>(cf.c[1]);
+    const A c2 = static_cast<A>(cf.c[2]), scale = static_cast<A>(cf.scale);
+    wsum += wd;
+    const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
+    const int edge_lane = xpos ? 0 : 63;
+#pragma unroll
+    for (int k = 0; k < RZ; ++k) {
+      const A nbr = __shfl(ik[k], src_lane, 64);
+      const A exk = read_lane(ex, k);
+      A ey = ey_r[k];
+      if constexpr (SHIFT) ey += ypos ? shy_p[k] : shy_n[k];
+      if (fok && k < nplanes) {
+        const A v = ik[k];
+        A acc = (in[k] - v) * a_inv_dt + (I0r[k] - v) * a_inv_tau;
+        if (xpos || xneg) {
+          const A up = xw ? static_cast<A>(xg_r[k]) : (lane == edge_lane ? exk : nbr);
+          acc += c0 * (up - v);
+        }
+        if (ypos || yneg) {
+          const A up = yw ? static_cast<A>(yg_r[k]) : ey;
+          acc += c1 * (up - v);
+        }
+        if (zpos) {
+          const A up = (k == 0) ? ez : ik[k > 0 ? k - 1 : 0];
+          acc += c2 * (up - v);
+        } else if (zneg) {
+          const A up = (k == nplanes - 1) ? ez : ik[k + 1 < RZ ? k + 1 : RZ - 1];
+          acc += c2 * (up - v);
+        }
+        const A inew = v + acc * scale;
+        buf_store<Real>(static_cast<Real>(inew), ro, vc[k], 0);
+        const double da = static_cast<double>(inew - v);
+        const double dn = static_cast<double>(inew - in[k]);
+        accumulate_energy<Real>(S[k], Sc[k], wd, static_cast<double>(inew));
+        num += wd * da * da;
+        den += wd * dn * dn;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RZ; ++k)
+    if (live && fok && k < nplanes)
+      p.S[((size_t)dg * g.nb + b) * ncp + vc[k] / sz] =
+          energy_partial<Real>(S[k], Sc[k], iref, wsum);
+
+  __shared__ double red[2][kSweepBlock / 64];
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (lane == 0) {
+    red[0][wave] = num;
+    red[1][wave] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int i = 0; i < kSweepBlock / 64; ++i) {
+      a += red[0][i];
+      c += red[1][i];
+    }
+    const size_t blk = ((size_t)bz * gy + by) * gx + bx;
+    p.part[2 * blk] = a;
+    p.part[2 * blk + 1] = c;
+  }
+}
+
+template <typename Real, int RZ, bool SHIFT>
+__global__ __launch_bounds__(kSweepBlock) void sweep3d_flat_kernel(const SweepParams<Real> p,
+                                                                   const int nft, const int dgs) {
+  if (step_done(p.ctl)) return;
+  flat3d_body<Real, RZ, SHIFT>(p, nft, dgs, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
+                               gridDim.y);
+}
+
 SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int rz,
                           int ndg, int kind) {
   SweepPlan pl{};
@@ -925,6 +1171,16 @@ SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int r
     pl.ntx = (nx + 63) / 64;
     pl.nty = (ny + 4 * ry - 1) / (4 * ry);
     pl.ntiles = pl.ntx * pl.nty;
+  } else if (dim == 3 && kind == kSweepFlat3D) {
+    pl.kind = kSweepFlat3D;
+    // 256 plane cells (4 waves x 64 lanes) x rz planes per workgroup
+    if (rz != 2 && rz != 4) rz = 4;
+    pl.ry = 0;
+    pl.rz = rz;
+    pl.ntx = (nx * ny + 255) / 256;
+    pl.nty = 1;
+    pl.ntz = (nz + rz - 1) / rz;
+    pl.ntiles = pl.ntx * pl.ntz;
   } else if (dim == 3 && kind != kSweepCellPerThread) {
     pl.kind = kSweepColumnWalk3D;
     // (rows, planes) per wave: 2 x 2 (default), 1 x 4 or 2 x 4
@@ -978,6 +1234,16 @@ static void launch_sweep_t(hipStream_t stream, const SweepPlan& plan, const Swee
                            stream, p, plan.ntx, plan.dgs);
         break;
     }
+    return;
+  }
+  if (plan.kind == kSweepFlat3D) {
+    const dim3 grid(plan.ntiles, g.nb, plan.ndg);
+    if (plan.rz == 2)
+      hipLaunchKernelGGL((sweep3d_flat_kernel<Real, 2, SHIFT>), grid, dim3(kSweepBlock), 0,
+                         stream, p, plan.ntx, plan.dgs);
+    else
+      hipLaunchKernelGGL((sweep3d_flat_kernel<Real, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+                         stream, p, plan.ntx, plan.dgs);
     return;
   }
   if (plan.kind == kSweepColumnWalk3D) {
@@ -1373,16 +1639,18 @@ __device__ __forceinline__ const SweepParams<float>& batch_params<float>(const B
 // One work item of a batched sweep.  The geometry's parameters live in device
 // memory (the source / destination iterates are rewritten there after every
 // iteration), and batches seed warm starts through the temperature only (no
-// intensity shift).  KIND is the column-walk family: 2D with 4 rows per wave,
-// or 3D with 2 rows x 2 planes or 1 row x 4 planes per wave, chosen per
-// geometry (both hold four cells per lane, so neither raises the kernel's
-// register count above the other's).
+// intensity shift).  KIND is the dimension's family: 2D with 4 rows per wave,
+// or 3D with 2 rows x 2 planes or 1 row x 4 planes per wave or the flattened
+// (x, y) plane with 2 planes per wave, chosen per geometry (none of them
+// raises the kernel's register count above the 2 x 2 walk's).
 template <typename Real, int KIND>
 __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w) {
   const SweepParams<Real>& p = batch_params<Real>(c);
   const SweepPlan& pl = c.plan;
   if constexpr (KIND == kSweepColumnWalk2D)
     walk2d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+  else if (__builtin_amdgcn_readfirstlane(pl.kind) == kSweepFlat3D)
+    flat3d_body<Real, 2, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else if (__builtin_amdgcn_readfirstlane(pl.ry) == 1)
     walk3d_body<Real, 1, 4, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
                                    p.g.nb);

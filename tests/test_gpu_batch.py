@@ -101,20 +101,23 @@ def test_batch_equals_solo_runs(gpu, use_graph, precision):
 @pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
 def test_batch_mixes_3d_layouts(gpu, monkeypatch, precision):
     """3D geometries of one batch may hold 2 rows x 2 planes or 1 row x 4
-    planes per wave; each still gives its solo result bit for bit."""
+    planes per wave (column walk), or 2 planes of the flattened (x, y) plane
+    (the default for these narrow meshes, used by the other batch tests);
+    each still gives its solo result bit for bit."""
     import torch
     insts = geometries(precision)
-    layouts = [None, (1, 4), None, (2, 2), None]
+    walk = 1  # kernel family of the column walks
+    layouts = [None, (walk, 1, 4), None, (walk, 2, 2), None]
     stream = torch.cuda.Stream()
     announce(f"batch with 3D layouts {layouts}, precision={precision}")
 
     def make(i):
-        if layouts[i]:
-            monkeypatch.setenv("BTE_SWEEP_RY", str(layouts[i][0]))
-            monkeypatch.setenv("BTE_SWEEP_RZ", str(layouts[i][1]))
-        else:
-            monkeypatch.delenv("BTE_SWEEP_RY", raising=False)
-            monkeypatch.delenv("BTE_SWEEP_RZ", raising=False)
+        names = ("BTE_SWEEP_KIND", "BTE_SWEEP_RY", "BTE_SWEEP_RZ")
+        for name, v in zip(names, layouts[i] or (None, None, None)):
+            if v is None:
+                monkeypatch.delenv(name, raising=False)
+            else:
+                monkeypatch.setenv(name, str(v))
         return gpu.Solver(insts[i], stream=stream)
 
     solos = []
@@ -178,7 +181,7 @@ def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
     else:
         inst = I.gaussian_3d(20, 18, 11, 2, 8, 6, seed=6, sigma_cells=2.5,
                              precision=I.PRECISION_FP64, nsteps=2)
-        shapes = {(2, 2), (1, 4), (2, 4)}
+        shapes = {(2, 2), (1, 4), (2, 4), (0, 4), (0, 2)}  # 0 rows: flattened plane
     announce(f"autotune {dim}D")
     with tempfile.TemporaryDirectory() as d:
         cache = os.path.join(d, "tune.txt")
@@ -199,4 +202,4 @@ def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
         assert open(cache).read() == text
         with gpu.Solver(inst) as s3:  # restricted to what a batch accepts
             ry, rz, ndg, ms = s3.autotune(None, batch=True)
-            assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4)}) and ms > 0
+            assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4), (0, 2)}) and ms > 0

@@ -4,8 +4,10 @@ Ragged meshes that span two x tiles (the last one partly filled), row and
 plane counts that are not multiples of a block, and a different wall kind on
 each face, so every edge path of the column-walk sweeps (neighbouring tile,
 isothermal table, mirrored direction; first and last rows, planes and lanes)
-is exercised in every layout.  FP64 within 1e-10 relative with the oracle's
-sweep schedule replayed; FP32 storage within 1e-5 relative in T.
+is exercised in every layout.  A narrow 3D mesh (13 cells along x) puts
+several rows, and x walls, inside one wave of the flattened-plane layout.
+FP64 within 1e-10 relative with the oracle's sweep schedule replayed; FP32
+storage within 1e-5 relative in T.
 """
 import sys
 
@@ -59,17 +61,32 @@ def case_3d():
     return mixed_walls(inst, 54)
 
 
+def case_3d_narrow():
+    inst = I.gaussian_3d(13, 9, 10, 2, 8, 3, seed=55, precision=I.PRECISION_FP64, nsteps=2)
+    inst.h = [1.1e-8, 0.8e-8, 1e-8]
+    inst.name = "layouts3d_13x9x10"
+    return mixed_walls(inst, 56)
+
+
+CASES = {"2d": case_2d, "3d": case_3d, "3dn": case_3d_narrow}
+KIND_WALK, KIND_FLAT = 1, 3  # kernel families (ry = 0: flattened (x, y) plane)
 LAYOUTS = [("2d", 4, 0, 1), ("2d", 8, 0, 3), ("2d", 16, 0, 2),
-           ("3d", 2, 2, 1), ("3d", 1, 4, 2), ("3d", 2, 4, 3)]
+           ("3d", 2, 2, 1), ("3d", 1, 4, 2), ("3d", 2, 4, 3), ("3d", 0, 4, 1), ("3d", 0, 2, 2),
+           ("3dn", 2, 2, 1), ("3dn", 1, 4, 3), ("3dn", 0, 4, 2), ("3dn", 0, 2, 1)]
+
+
+def set_layout(monkeypatch, ry, rz, ndg):
+    monkeypatch.setenv("BTE_SWEEP_KIND", str(KIND_FLAT if ry == 0 else KIND_WALK))
+    monkeypatch.setenv("BTE_SWEEP_RY", str(ry))
+    monkeypatch.setenv("BTE_SWEEP_RZ", str(rz))
+    monkeypatch.setenv("BTE_SWEEP_NDG", str(ndg))
 
 
 @pytest.mark.parametrize("dim,ry,rz,ndg", LAYOUTS)
 def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     from oracle import Oracle
-    inst = case_2d() if dim == "2d" else case_3d()
-    monkeypatch.setenv("BTE_SWEEP_RY", str(ry))
-    monkeypatch.setenv("BTE_SWEEP_RZ", str(rz))
-    monkeypatch.setenv("BTE_SWEEP_NDG", str(ndg))
+    inst = CASES[dim]()
+    set_layout(monkeypatch, ry, rz, ndg)
     ref = Oracle(inst)
     sched = [s["inner"] for s in ref.run(inst.nsteps)]
     announce(f"{inst.name} ry={ry} rz={rz} ndg={ndg} sched={sched}")
@@ -83,13 +100,12 @@ def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     assert errT <= 1e-10 and errI <= 1e-10
 
 
-@pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("3d", 1, 4, 2)])
+@pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("3d", 1, 4, 2), ("3d", 0, 4, 1),
+                                             ("3dn", 0, 2, 2)])
 def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     from oracle import Oracle
-    inst = case_2d() if dim == "2d" else case_3d()
-    monkeypatch.setenv("BTE_SWEEP_RY", str(ry))
-    monkeypatch.setenv("BTE_SWEEP_RZ", str(rz))
-    monkeypatch.setenv("BTE_SWEEP_NDG", str(ndg))
+    inst = CASES[dim]()
+    set_layout(monkeypatch, ry, rz, ndg)
     ref = Oracle(inst)
     sched = [s["inner"] for s in ref.run(inst.nsteps)]
     announce(f"{inst.name} fp32 ry={ry} rz={rz} ndg={ndg}")
@@ -99,3 +115,28 @@ def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     errT = float(np.max(np.abs(T - ref.temperature()) / ref.temperature()))
     print(f"fp32 T {errT:.2e}", flush=True)
     assert errT <= 1e-5
+
+
+@pytest.mark.parametrize("dim", ["3d", "3dn"])
+def test_warm_start_shift_is_layout_independent(gpu, monkeypatch, dim):
+    """The first sweep of a warm-started step adds the equilibrium shift at the
+    guessed temperature to every inflow value (neighbour, edge, mirrored
+    ghost).  The trained network is deterministic, so every 3D layout must
+    give the same temperatures; the walk with 2 x 2 per wave is the one the
+    oracle checks in the other tests."""
+    inst = CASES[dim]()
+    inst.nsteps = 6
+    opts = dict(warm_start=gpu.BTE_WARM_T_SHIFT, nn_train_steps=3, nn_seed=4)
+    results = {}
+    for ry, rz in ((2, 2), (1, 4), (0, 4), (0, 2)):
+        set_layout(monkeypatch, ry, rz, 1)
+        announce(f"{inst.name} warm start with shift, layout ry={ry} rz={rz}")
+        with gpu.Solver(inst, **opts) as sol:
+            st = sol.step(6, fixed_inner=[8] * 6)
+            assert all(x["warm"] for x in st[3:])
+            results[(ry, rz)] = sol.temperature()
+    ref = results[(2, 2)]
+    for key, T in results.items():
+        err = float(np.max(np.abs(T - ref) / ref))
+        print(f"layout {key}: max rel diff {err:.2e}", flush=True)
+        assert err <= 1e-12
