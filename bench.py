@@ -112,7 +112,7 @@ def run_solo(bte, inst, prec, steps, label, timing=False, **opts):
     t0 = time.perf_counter()
     stats, done = [], 0
     while done < steps:
-        n = min(20, steps - done)
+        n = min(10, steps - done)
         stats += sol.step(n)
         done += n
         log(f"{label}: steps {done}/{steps}, inner last={stats[-1]['inner']}")

@@ -229,8 +229,7 @@ int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const
  * 2 planes of the flattened (x, y) plane (reported as 0 rows), x 1-4
  * direction groups.  *ry and *rz are in/out: a positive value on entry
  * restricts the search to that row / plane count, and *ry = -1 to the layouts
- * a batch accepts (4 rows in 2D; 2x2, 1x4 or the flattened plane with 2
- * planes in 3D).  The choice is returned in *ry, *rz, *ndg and its sweep time
+ * a batch accepts (4 rows in 2D; 2x2, 1x4 or the flattened plane in 3D).  The choice is returned in *ry, *rz, *ndg and its sweep time
  * (measured now or recorded in the cache) in *sweep_ms (all nullable; -1 for
  * shapes with a single layout).  BTE_E_INVAL if the restriction matches no
  * layout. */

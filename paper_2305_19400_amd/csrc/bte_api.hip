@@ -66,11 +66,11 @@ struct Shape {
 
 // The layouts a batched persistent sweep compiles: 4 rows per wave in 2D;
 // in 3D 2 rows x 2 planes or 1 row x 4 planes per wave, or the flattened
-// (x, y) plane with 2 planes per wave.
+// (x, y) plane with 2 or 4 planes per wave.
 bool batch_layout(int kind, int ry, int rz) {
   if (kind == kSweepColumnWalk2D) return ry == 4;
   if (kind == kSweepColumnWalk3D) return (ry == 2 && rz == 2) || (ry == 1 && rz == 4);
-  if (kind == kSweepFlat3D) return rz == 2;
+  if (kind == kSweepFlat3D) return rz == 2 || rz == 4;
   return false;
 }
 
@@ -179,17 +179,17 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   // BTE_SWEEP_KIND override the rows and planes per wave, the number of
   // direction groups and the kernel family (tuning knobs).  3D defaults: when
   // 64-column tiles would leave more than an eighth of the lanes idle (a
-  // narrow mesh or a ragged last tile), the flattened (x, y) plane with 2
-  // planes per wave (as fast as 4 planes there, and batches accept it);
-  // otherwise 2 rows x 2 planes per wave with FP64 storage and 1 row x 4
-  // planes with FP32 storage (the faster at 64^3 cells).
+  // narrow mesh or a ragged last tile), the flattened (x, y) plane, with 4
+  // planes per wave for FP32 storage and 2 for FP64 storage (whose registers
+  // allow fewer waves); otherwise 2 rows x 2 planes per wave with FP64
+  // storage and 1 row x 4 planes with FP32 storage (the faster at 64^3).
   const bool fp32 = o->precision != BTE_FP64;
   int ry_dflt = 0, rz_dflt = 0, kind_dflt = -1;
   if (s.dim == 3) {
     const double lanes_used = (double)s.nx / (64.0 * ((s.nx + 63) / 64));
     if (lanes_used < 0.875) {
       kind_dflt = kSweepFlat3D;
-      rz_dflt = 2;
+      rz_dflt = fp32 ? 4 : 2;
     } else if (fp32) {
       ry_dflt = 1;
       rz_dflt = 4;
@@ -1139,11 +1139,11 @@ struct bte_batch {
   BatchCtx* d_ctx;
   BatchCtx* h_ctx;  // pinned staging
   BatchItem* d_items;
-  int n2d, n3d;
+  int counts[kBatchLists];  // items per work list, stored back to back
   BatchControl* d_bc;
   BatchControl* h_bc;  // pinned
   Control* h_ctl;      // pinned, one per geometry
-  int sweep_blocks[2];
+  int sweep_blocks[kBatchLists];
   int temp_blocks;
   int max_inner;
   bool use_graph;
@@ -1166,7 +1166,7 @@ int batch_enqueue_iteration(bte_batch* b) {
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   } else {
     HIP_TRY(launch_batch_iteration(b->stream, b->precision, b->d_ctx, (int)b->ctx.size(),
-                                   b->d_items, b->n2d, b->n3d, b->d_bc, b->sweep_blocks,
+                                   b->d_items, b->counts, b->d_bc, b->sweep_blocks,
                                    b->temp_blocks));
     HIP_TRY(hipMemcpyAsync(b->h_bc, b->d_bc, sizeof(BatchControl), hipMemcpyDeviceToHost,
                            b->stream));
@@ -1195,7 +1195,8 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
     const SweepPlan& pl = c->s.plan;
     if (!batch_layout(pl.kind, pl.ry, pl.rz))
       return fail(BTE_E_INVAL,
-                  "batches need the 4-row 2D or the 2x2 or 1x4 3D column-walk layout (context %d)", i);
+                  "batches need the 4-row 2D, the 2x2 or 1x4 3D column-walk or the flattened-plane "
+      "layout (context %d)", i);
     if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(BTE_E_INVAL, "context %d appears twice", i);
@@ -1210,7 +1211,8 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   b->exec = nullptr;
   for (auto& e : b->ev) e = nullptr;
   b->max_inner = 0;
-  // work list: 2D items then 3D items, each ordered largest geometry first
+  // work lists (2D; 3D; 3D flattened plane with 4 planes), each ordered
+  // largest geometry first
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -1218,26 +1220,30 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
     const double wc = (double)ctxs[c]->s.nc * ctxs[c]->s.nd * ctxs[c]->s.nb;
     return wa > wc;
   });
-  std::vector<BatchItem> items2, items3;
+  std::vector<BatchItem> lists[kBatchLists];
   for (int i : order) {
     const SweepPlan& pl = ctxs[i]->s.plan;
-    auto& dst = pl.kind == kSweepColumnWalk2D ? items2 : items3;
+    auto& dst = pl.kind == kSweepColumnWalk2D                  ? lists[kList2D]
+                : (pl.kind == kSweepFlat3D && pl.rz == 4) ? lists[kListFlat4]
+                                                          : lists[kList3D];
     const int nz = pl.ndg;  // direction groups
     for (int bz = 0; bz < nz; ++bz)
       for (int by = 0; by < ctxs[i]->s.nb; ++by)
         for (int bx = 0; bx < pl.ntiles; ++bx) dst.push_back(BatchItem{i, bx, by, bz});
     b->max_inner = std::max(b->max_inner, ctxs[i]->opt.max_inner);
   }
-  b->n2d = (int)items2.size();
-  b->n3d = (int)items3.size();
-  items2.insert(items2.end(), items3.begin(), items3.end());
+  std::vector<BatchItem> items;
+  for (int l = 0; l < kBatchLists; ++l) {
+    b->counts[l] = (int)lists[l].size();
+    items.insert(items.end(), lists[l].begin(), lists[l].end());
+  }
   int cus = 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  b->sweep_blocks[0] = cus * batch_sweep_occupancy(b->precision, kSweepColumnWalk2D);
-  b->sweep_blocks[1] = cus * batch_sweep_occupancy(b->precision, kSweepColumnWalk3D);
+  for (int l = 0; l < kBatchLists; ++l)
+    b->sweep_blocks[l] = cus * batch_sweep_occupancy(b->precision, l);
   int blocks = 0;
   for (int i = 0; i < n; ++i) blocks += (ctxs[i]->s.nc + 31) / 32;
   b->temp_blocks = blocks;
@@ -1257,19 +1263,19 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   b->h_ctl = nullptr;
   BATCH_TRY(hipMalloc((void**)&b->d_ctx, sizeof(BatchCtx) * n));
   BATCH_TRY(hipHostMalloc((void**)&b->h_ctx, sizeof(BatchCtx) * n));
-  BATCH_TRY(hipMalloc((void**)&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items2.size())));
+  BATCH_TRY(hipMalloc((void**)&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items.size())));
   BATCH_TRY(hipMalloc((void**)&b->d_bc, sizeof(BatchControl)));
   BATCH_TRY(hipHostMalloc((void**)&b->h_bc, sizeof(BatchControl)));
   BATCH_TRY(hipHostMalloc((void**)&b->h_ctl, sizeof(Control) * n));
   for (auto& e : b->ev) BATCH_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  if (!items2.empty())
-    BATCH_TRY(hipMemcpyAsync(b->d_items, items2.data(), sizeof(BatchItem) * items2.size(),
+  if (!items.empty())
+    BATCH_TRY(hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
                              hipMemcpyHostToDevice, b->stream));
   BATCH_TRY(hipStreamSynchronize(b->stream));
   if (b->use_graph) {
     BATCH_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const hipError_t e1 = launch_batch_iteration(b->stream, b->precision, b->d_ctx, n, b->d_items,
-                                                 b->n2d, b->n3d, b->d_bc, b->sweep_blocks,
+                                                 b->counts, b->d_bc, b->sweep_blocks,
                                                  b->temp_blocks);
     const hipError_t e2 = hipMemcpyAsync(b->h_bc, b->d_bc, sizeof(BatchControl),
                                          hipMemcpyDeviceToHost, b->stream);

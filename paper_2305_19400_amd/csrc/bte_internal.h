@@ -161,20 +161,30 @@ struct BatchItem {
 };
 
 struct BatchControl {
-  int next_item;  // persistent-sweep work counter (2D list)
-  int iteration;  // batched iterations completed
-  int active;     // geometries not yet converged after the last iteration
-  int pad;        // persistent-sweep work counter (3D list)
+  int next_item;     // persistent-sweep work counter (2D list)
+  int iteration;     // batched iterations completed
+  int active;        // geometries not yet converged after the last iteration
+  int next_item3d;   // persistent-sweep work counter (3D list)
+  int next_item_f4;  // persistent-sweep work counter (3D flattened-plane 4-plane list)
+  int pad[3];
 };
+
+// Work lists of a batch, one persistent launch each: 2D column walks; 3D
+// column walks and the flattened plane with 2 planes; the flattened plane
+// with 4 planes (a kernel of its own, since it needs more registers).
+enum BatchList { kList2D = 0, kList3D = 1, kListFlat4 = 2, kBatchLists = 3 };
 
 // One inner iteration of every geometry: persistent sweep over the work list,
 // temperature inversion, per-geometry control, active count (+ reset of the
 // work counter for the next iteration).
+// items holds the lists back to back; counts[l] and sweep_blocks[l] per BatchList.
 hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* ctxs,
-                                  int nctx, const BatchItem* items, int n2d, int n3d,
-                                  BatchControl* bc, const int sweep_blocks[2], int temp_blocks);
+                                  int nctx, const BatchItem* items,
+                                  const int counts[kBatchLists], BatchControl* bc,
+                                  const int sweep_blocks[kBatchLists], int temp_blocks);
 hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, BatchControl* bc);
-int batch_sweep_occupancy(int precision, int kind);
+// Resident workgroups per compute unit of one list's persistent sweep kernel.
+int batch_sweep_occupancy(int precision, int list);
 
 hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* T, double* I0, double* E);

@@ -74,21 +74,22 @@ struct Storage<double> {
 template <>
 struct Storage<float> {
   static constexpr bool kDeviation = true;
-  using Arith = float;
+  using Arith = double;
 };
 
-// Arithmetic of the column-walk sweeps.  With FP64 storage it runs on the
-// intensities in FP64.  With FP32 storage it runs in FP32 on the stored
-// deviations I - Iref_b: every term of the point-Jacobi update is a difference
-// of two intensities of one band (I^n - I, I0 - I, I_upwind - I), so Iref_b
-// cancels and the update loses nothing beyond the rounding of the stored
-// value; the energy sum (compensated) and the norms stay FP64.
+// Arithmetic of the column-walk sweeps: FP64 on the intensities (FP64
+// storage) or on the deviations I - Iref_b (FP32 storage).  Every term of the
+// point-Jacobi update is a difference of two intensities of one band
+// (I^n - I, I0 - I, I_upwind - I), so Iref_b cancels, and the update is
+// rounded once, to the stored value.  (The update computed in FP32 leaves
+// rounding noise of an ulp in every increment: a converged iterate keeps
+// flickering and the increment norm stalls far above tight tolerances.)
 template <typename Real>
 using Arith = typename Storage<Real>::Arith;
 // Arithmetic value of an FP64 intensity (cell equilibrium, warm-start shift).
 template <typename Real>
 __device__ __forceinline__ Arith<Real> to_arith(double iref, double I) {
-  if constexpr (Storage<Real>::kDeviation) return static_cast<float>(I - iref);
+  if constexpr (Storage<Real>::kDeviation) return I - iref;
   else return I;
 }
 
@@ -557,8 +558,11 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
           const A up = (j == nrows - 1) ? ey : ik[j + 1 < RY ? j + 1 : RY - 1];
           acc += c1 * (up - v);
         }
-        const A inew = v + acc * scale;
-        buf_store<Real>(static_cast<Real>(inew), ro, vrow[j], 0);
+        // the stored value drives the norms and the energy: once the
+        // iterate stops changing in storage precision its increment is zero
+        const Real inew_r = static_cast<Real>(v + acc * scale);
+        buf_store<Real>(inew_r, ro, vrow[j], 0);
+        const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
         const double dn = static_cast<double>(inew - in[j]);
         accumulate_energy<Real>(S[j], Sc[j], wd, static_cast<double>(inew));
@@ -857,8 +861,11 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
             const A up = (k == nplanes - 1) ? ez[j] : ik[j][k + 1 < RZ ? k + 1 : RZ - 1];
             acc += c2 * (up - v);
           }
-          const A inew = v + acc * scale;
-          buf_store<Real>(static_cast<Real>(inew), ro, vc[j][k], 0);
+          // the stored value drives the norms and the energy: once the
+          // iterate stops changing in storage precision its increment is zero
+          const Real inew_r = static_cast<Real>(v + acc * scale);
+          buf_store<Real>(inew_r, ro, vc[j][k], 0);
+          const A inew = inew_r;
           const double da = static_cast<double>(inew - v);
           const double dn = static_cast<double>(inew - in[j][k]);
           accumulate_energy<Real>(S[j][k], Sc[j][k], wd, static_cast<double>(inew));
@@ -1044,9 +1051,9 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
     // x and y walls: lanes on a wall load their ghosts (masked to them)
     const bool xw = (xpos && x == 0) || (xneg && x == nx - 1);
     const bool yw = (ypos && y == 0) || (yneg && y == ny - 1);
-    Real xg_r[RZ], yg_r[RZ];
+    A xg[RZ], yg[RZ];
 #pragma unroll
-    for (int k = 0; k < RZ; ++k) xg_r[k] = yg_r[k] = 0;
+    for (int k = 0; k < RZ; ++k) xg[k] = yg[k] = 0;
     if (xw) {
       const int fx = xpos ? 0 : 1;
       const bool iso = p.t.wall[fx] == 0;
@@ -1054,11 +1061,11 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
                          : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)d) * ncp, slab_bytes);
 #pragma unroll
       for (int k = 0; k < RZ; ++k)
-        xg_r[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fx] + y + ny * zp[k]) * sz : vc[k]);
+        xg[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fx] + y + ny * zp[k]) * sz : vc[k]);
       if constexpr (SHIFT)
         if (!iso)
 #pragma unroll
-          for (int k = 0; k < RZ; ++k) xg_r[k] = static_cast<Real>(xg_r[k] + sh[k]);
+          for (int k = 0; k < RZ; ++k) xg[k] += sh[k];
     }
     if (yw) {
       const int fyw = ypos ? 2 : 3;
@@ -1068,11 +1075,11 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
                                      slab_bytes);
 #pragma unroll
       for (int k = 0; k < RZ; ++k)
-        yg_r[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fyw] + x + nx * zp[k]) * sz : vc[k]);
+        yg[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fyw] + x + nx * zp[k]) * sz : vc[k]);
       if constexpr (SHIFT)
         if (!iso)
 #pragma unroll
-          for (int k = 0; k < RZ; ++k) yg_r[k] = static_cast<Real>(yg_r[k] + sh[k]);
+          for (int k = 0; k < RZ; ++k) yg[k] += sh[k];
     }
     A ex = ex_r, ez = ez_r;
     if constexpr (SHIFT) {
@@ -1101,11 +1108,11 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
         const A v = ik[k];
         A acc = (in[k] - v) * a_inv_dt + (I0r[k] - v) * a_inv_tau;
         if (xpos || xneg) {
-          const A up = xw ? static_cast<A>(xg_r[k]) : (lane == edge_lane ? exk : nbr);
+          const A up = xw ? xg[k] : (lane == edge_lane ? exk : nbr);
           acc += c0 * (up - v);
         }
         if (ypos || yneg) {
-          const A up = yw ? static_cast<A>(yg_r[k]) : ey;
+          const A up = yw ? yg[k] : ey;
           acc += c1 * (up - v);
         }
         if (zpos) {
@@ -1115,8 +1122,11 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
           const A up = (k == nplanes - 1) ? ez : ik[k + 1 < RZ ? k + 1 : RZ - 1];
           acc += c2 * (up - v);
         }
-        const A inew = v + acc * scale;
-        buf_store<Real>(static_cast<Real>(inew), ro, vc[k], 0);
+        // the stored value drives the norms and the energy: once the
+        // iterate stops changing in storage precision its increment is zero
+        const Real inew_r = static_cast<Real>(v + acc * scale);
+        buf_store<Real>(inew_r, ro, vc[k], 0);
+        const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
         const double dn = static_cast<double>(inew - in[k]);
         accumulate_energy<Real>(S[k], Sc[k], wd, static_cast<double>(inew));
@@ -1639,16 +1649,19 @@ __device__ __forceinline__ const SweepParams<float>& batch_params<float>(const B
 // One work item of a batched sweep.  The geometry's parameters live in device
 // memory (the source / destination iterates are rewritten there after every
 // iteration), and batches seed warm starts through the temperature only (no
-// intensity shift).  KIND is the dimension's family: 2D with 4 rows per wave,
-// or 3D with 2 rows x 2 planes or 1 row x 4 planes per wave or the flattened
-// (x, y) plane with 2 planes per wave, chosen per geometry (none of them
-// raises the kernel's register count above the 2 x 2 walk's).
-template <typename Real, int KIND>
+// intensity shift).  LIST is the work list: 2D with 4 rows per wave; 3D with
+// 2 rows x 2 planes or 1 row x 4 planes per wave or the flattened (x, y)
+// plane with 2 planes per wave, chosen per geometry (none of them raises the
+// kernel's register count above the 2 x 2 walk's); or the flattened plane
+// with 4 planes per wave.
+template <typename Real, int LIST>
 __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w) {
   const SweepParams<Real>& p = batch_params<Real>(c);
   const SweepPlan& pl = c.plan;
-  if constexpr (KIND == kSweepColumnWalk2D)
+  if constexpr (LIST == kList2D)
     walk2d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+  else if constexpr (LIST == kListFlat4)
+    flat3d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else if (__builtin_amdgcn_readfirstlane(pl.kind) == kSweepFlat3D)
     flat3d_body<Real, 2, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else if (__builtin_amdgcn_readfirstlane(pl.ry) == 1)
@@ -1671,7 +1684,7 @@ __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w
 // makes the loop's continuation divergent: lanes other than thread 0 then
 // circle the barrier re-reading a stale item while thread 0 waits outside the
 // inner loop, and the kernel never finishes.
-template <typename Real, int KIND>
+template <typename Real, int LIST>
 __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx* __restrict__ ctxs,
                                                                   const BatchItem* __restrict__ items,
                                                                   int nitems, int* next_item) {
@@ -1689,7 +1702,7 @@ __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx
     w.by = __builtin_amdgcn_readfirstlane(items[it].by);
     w.bz = __builtin_amdgcn_readfirstlane(items[it].bz);
     const BatchCtx& c = ctxs[w.ctx];
-    if (!step_done(c.ctl)) batch_item<Real, KIND>(c, w);
+    if (!step_done(c.ctl)) batch_item<Real, LIST>(c, w);
     if (threadIdx.x == 0) item_s = atomicAdd(next_item, 1);
   }
 }
@@ -1728,7 +1741,8 @@ __global__ void batch_count_kernel(const BatchCtx* __restrict__ ctxs, int nctx, 
   bc->active = active;
   bc->iteration += 1;
   bc->next_item = 0;
-  bc->pad = 0;
+  bc->next_item3d = 0;
+  bc->next_item_f4 = 0;
 }
 
 __global__ void batch_reset_kernel(BatchCtx* ctxs, int nctx, BatchControl* bc) {
@@ -1753,28 +1767,39 @@ __global__ void batch_reset_kernel(BatchCtx* ctxs, int nctx, BatchControl* bc) {
     bc->next_item = 0;
     bc->iteration = 0;
     bc->active = nctx;
-    bc->pad = 0;
+    bc->next_item3d = 0;
+    bc->next_item_f4 = 0;
   }
 }
 
 template <typename Real>
 static void launch_batch_sweeps(hipStream_t stream, const BatchCtx* ctxs, const BatchItem* items,
-                                int n2d, int n3d, BatchControl* bc, const int blocks[2]) {
-  // the 2D and 3D work lists are consumed by two persistent launches, each
-  // compiled for one kernel family so neither pays the other's registers
-  if (n2d > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, kSweepColumnWalk2D>), dim3(blocks[0]),
-                       dim3(kSweepBlock), 0, stream, ctxs, items, n2d, &bc->next_item);
-  if (n3d > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, kSweepColumnWalk3D>), dim3(blocks[1]),
-                       dim3(kSweepBlock), 0, stream, ctxs, items + n2d, n3d, &bc->pad);
+                                const int counts[kBatchLists], BatchControl* bc,
+                                const int blocks[kBatchLists]) {
+  // each work list is consumed by its own persistent launch, compiled for
+  // that list's layouts only, so no list pays another's registers
+  const BatchItem* list = items;
+  if (counts[kList2D] > 0)
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kList2D>), dim3(blocks[kList2D]),
+                       dim3(kSweepBlock), 0, stream, ctxs, list, counts[kList2D], &bc->next_item);
+  list += counts[kList2D];
+  if (counts[kList3D] > 0)
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kList3D>), dim3(blocks[kList3D]),
+                       dim3(kSweepBlock), 0, stream, ctxs, list, counts[kList3D],
+                       &bc->next_item3d);
+  list += counts[kList3D];
+  if (counts[kListFlat4] > 0)
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kListFlat4>), dim3(blocks[kListFlat4]),
+                       dim3(kSweepBlock), 0, stream, ctxs, list, counts[kListFlat4],
+                       &bc->next_item_f4);
 }
 
 hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* ctxs,
-                                  int nctx, const BatchItem* items, int n2d, int n3d,
-                                  BatchControl* bc, const int sweep_blocks[2], int temp_blocks) {
-  if (precision == 0) launch_batch_sweeps<double>(stream, ctxs, items, n2d, n3d, bc, sweep_blocks);
-  else launch_batch_sweeps<float>(stream, ctxs, items, n2d, n3d, bc, sweep_blocks);
+                                  int nctx, const BatchItem* items,
+                                  const int counts[kBatchLists], BatchControl* bc,
+                                  const int sweep_blocks[kBatchLists], int temp_blocks) {
+  if (precision == 0) launch_batch_sweeps<double>(stream, ctxs, items, counts, bc, sweep_blocks);
+  else launch_batch_sweeps<float>(stream, ctxs, items, counts, bc, sweep_blocks);
   hipLaunchKernelGGL(batch_temperature_kernel, dim3(temp_blocks), dim3(256), 0, stream, ctxs, nctx);
   hipLaunchKernelGGL(batch_control_kernel, dim3(nctx), dim3(kReduceBlock), 0, stream, ctxs);
   hipLaunchKernelGGL(batch_count_kernel, dim3(1), dim3(64), 0, stream, ctxs, nctx, bc);
@@ -1786,20 +1811,25 @@ hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, Batc
   return hipGetLastError();
 }
 
-int batch_sweep_occupancy(int precision, int kind) {
+template <typename Real>
+static hipError_t list_occupancy(int* n, int list) {
+  switch (list) {
+    case kList2D:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, batch_sweep_kernel<Real, kList2D>, kSweepBlock, 0);
+    case kList3D:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, batch_sweep_kernel<Real, kList3D>, kSweepBlock, 0);
+    default:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          n, batch_sweep_kernel<Real, kListFlat4>, kSweepBlock, 0);
+  }
+}
+
+int batch_sweep_occupancy(int precision, int list) {
   int n = 0;
-  hipError_t e;
-  const bool w2 = kind == kSweepColumnWalk2D;
-  if (precision == 0)
-    e = w2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &n, batch_sweep_kernel<double, kSweepColumnWalk2D>, kSweepBlock, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &n, batch_sweep_kernel<double, kSweepColumnWalk3D>, kSweepBlock, 0);
-  else
-    e = w2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &n, batch_sweep_kernel<float, kSweepColumnWalk2D>, kSweepBlock, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &n, batch_sweep_kernel<float, kSweepColumnWalk3D>, kSweepBlock, 0);
+  const hipError_t e =
+      precision == 0 ? list_occupancy<double>(&n, list) : list_occupancy<float>(&n, list);
   if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }

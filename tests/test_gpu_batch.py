@@ -98,16 +98,20 @@ def test_batch_equals_solo_runs(gpu, use_graph, precision):
         s.close()
 
 
+WALK, FLAT = 1, 3  # kernel families: column walk, flattened (x, y) plane
+
+
+@pytest.mark.parametrize("layout3d", [((WALK, 1, 4), (WALK, 2, 2)), ((FLAT, 0, 2), (FLAT, 0, 4))])
 @pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
-def test_batch_mixes_3d_layouts(gpu, monkeypatch, precision):
+def test_batch_mixes_3d_layouts(gpu, monkeypatch, precision, layout3d):
     """3D geometries of one batch may hold 2 rows x 2 planes or 1 row x 4
-    planes per wave (column walk), or 2 planes of the flattened (x, y) plane
-    (the default for these narrow meshes, used by the other batch tests);
-    each still gives its solo result bit for bit."""
+    planes per wave (column walk), or 2 or 4 planes of the flattened (x, y)
+    plane (the default for these narrow meshes, used by the other batch
+    tests; 4 planes run in a persistent launch of their own); each still
+    gives its solo result bit for bit."""
     import torch
     insts = geometries(precision)
-    walk = 1  # kernel family of the column walks
-    layouts = [None, (walk, 1, 4), None, (walk, 2, 2), None]
+    layouts = [None, layout3d[0], None, layout3d[1], None]
     stream = torch.cuda.Stream()
     announce(f"batch with 3D layouts {layouts}, precision={precision}")
 
@@ -202,4 +206,5 @@ def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
         assert open(cache).read() == text
         with gpu.Solver(inst) as s3:  # restricted to what a batch accepts
             ry, rz, ndg, ms = s3.autotune(None, batch=True)
-            assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4), (0, 2)}) and ms > 0
+            assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4), (0, 2), (0, 4)})
+            assert ms > 0

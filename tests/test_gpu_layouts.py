@@ -140,3 +140,18 @@ def test_warm_start_shift_is_layout_independent(gpu, monkeypatch, dim):
         err = float(np.max(np.abs(T - ref) / ref))
         print(f"layout {key}: max rel diff {err:.2e}", flush=True)
         assert err <= 1e-12
+
+
+@pytest.mark.parametrize("dim,ry,rz", [("2d", 4, 0), ("3d", 1, 4), ("3dn", 0, 2), ("3d", 0, 4)])
+def test_fp32_reaches_tight_tolerance(gpu, monkeypatch, dim, ry, rz):
+    """With FP32 storage the iterate must settle: the update is rounded once to
+    the stored value and the norms use that value, so a converged sweep
+    changes nothing and the increment norm falls to zero instead of stalling
+    at rounding noise.  Each step must stop well before the sweep cap."""
+    inst = CASES[dim]()
+    set_layout(monkeypatch, ry, rz, 1)
+    announce(f"{inst.name} fp32 tol 1e-10 ry={ry} rz={rz}")
+    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED, tol=1e-10, max_inner=200) as sol:
+        st = sol.step(3)
+    print([x["inner"] for x in st], flush=True)
+    assert all(x["converged"] and x["inner"] < 100 for x in st)
