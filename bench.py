@@ -120,8 +120,15 @@ def run_solo(bte, inst, prec, steps, label, timing=False, **opts):
     wall = time.perf_counter() - t0
     sweep_ms, nsweeps = sol.sweep_time()
     T = sol.temperature()
+    layout = sol.sweep_layout()
     sol.close()
-    return {"wall": wall, "stats": stats, "T": T, "sweep_ms": sweep_ms, "nsweeps": nsweeps}
+    return {"wall": wall, "stats": stats, "T": T, "sweep_ms": sweep_ms, "nsweeps": nsweeps,
+            "layout": layout}
+
+
+# sweep kernel of each layout family (bte_sweep_layout's kind)
+SWEEP_KERNELS = {0: "sweep_kernel", 1: "sweep2d_walk_kernel", 2: "sweep3d_walk_kernel",
+                 3: "sweep3d_flat_kernel"}
 
 
 def max_rel(a, b):
@@ -348,7 +355,8 @@ def main():
         "T_max_K": float(T.max()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep2d_walk_kernel" if inst.dim == 2 else "sweep3d_walk_kernel",
+                     "kernel": SWEEP_KERNELS[main_run["layout"]["kind"]],
+                     "layout": main_run["layout"],
                      "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
     }

@@ -197,6 +197,13 @@ int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size
  * (options.timing must be set); resets the accumulators. */
 int bte_sweep_time(bte_ctx* ctx, double* total_ms, int* count);
 
+/* The sweep layout in use (all nullable): kernel family (0 one cell per
+ * thread, 1 2D column walk, 2 3D column walk, 3 3D flattened (x, y) plane),
+ * rows walked per wave (0 for the flattened plane), planes held per wave
+ * (1 in 2D) and direction groups.  Chosen at create (BTE_SWEEP_* variables
+ * override it) or by bte_autotune. */
+int bte_sweep_layout(bte_ctx* ctx, int* kind, int* ry, int* rz, int* ndg);
+
 /* Learned warm start.  The parameter vector (FP32) is, in order:
  * W1[128][KP] | b1[128] | W2[128][128] | b2[128] | w3[128] | b3, 3 zeros |
  * mu_T, s_T, mu_E, s_E, s_D, 3 zeros

@@ -32,7 +32,8 @@ BTE_WARM_NONE, BTE_WARM_T, BTE_WARM_T_SHIFT = 0, 1, 2
 
 # every symbol include/bte.h declares
 EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "bte_intensity",
-           "bte_energy", "bte_set_state", "bte_sweep_time", "bte_nn_param_count", "bte_nn_params",
+           "bte_energy", "bte_set_state", "bte_sweep_time", "bte_sweep_layout",
+           "bte_nn_param_count", "bte_nn_params",
            "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_autotune",
            "bte_batch_create", "bte_batch_step", "bte_batch_destroy", "bte_destroy",
            "bte_last_error")
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.bte_energy.argtypes = [C.c_void_p, _dp, C.c_size_t]
     lib.bte_set_state.argtypes = [C.c_void_p, _dp, C.c_size_t, _dp, C.c_size_t]
     lib.bte_sweep_time.argtypes = [C.c_void_p, _dp, _ip]
+    lib.bte_sweep_layout.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip]
     _fp = C.POINTER(C.c_float)
     lib.bte_nn_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
     lib.bte_nn_params.argtypes = [C.c_void_p, _fp, C.c_size_t]
@@ -305,6 +307,14 @@ class Solver:
         _check(self.lib.bte_autotune(self._ctx, cache_path.encode() if cache_path else None,
                                      C.byref(ry_), C.byref(rz_), C.byref(ndg), C.byref(ms)))
         return ry_.value, rz_.value, ndg.value, ms.value
+
+    def sweep_layout(self) -> dict:
+        """The sweep layout in use: kernel family (0 cell per thread, 1 2D column
+        walk, 2 3D column walk, 3 3D flattened plane), rows and planes per wave,
+        direction groups."""
+        v = [C.c_int(0) for _ in range(4)]
+        _check(self.lib.bte_sweep_layout(self._ctx, *[C.byref(x) for x in v]))
+        return dict(zip(("kind", "ry", "rz", "ndg"), (x.value for x in v)))
 
     def sweep_time(self):
         """(total ms, count) of sweep kernels timed since the last call."""

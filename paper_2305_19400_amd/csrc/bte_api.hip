@@ -986,6 +986,16 @@ int bte_sweep_time(bte_ctx* ctx, double* total_ms, int* count) {
   return BTE_OK;
 }
 
+int bte_sweep_layout(bte_ctx* ctx, int* kind, int* ry, int* rz, int* ndg) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  const SweepPlan& pl = ctx->s.plan;
+  if (kind) *kind = pl.kind;
+  if (ry) *ry = pl.ry;
+  if (rz) *rz = pl.rz;
+  if (ndg) *ndg = pl.ndg;
+  return BTE_OK;
+}
+
 int bte_destroy(bte_ctx* ctx) {
   if (!ctx) return BTE_OK;
   (void)hipStreamSynchronize(ctx->stream);

@@ -91,6 +91,8 @@ def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     sched = [s["inner"] for s in ref.run(inst.nsteps)]
     announce(f"{inst.name} ry={ry} rz={rz} ndg={ndg} sched={sched}")
     with gpu.Solver(inst) as sol:
+        kind = KIND_FLAT if ry == 0 else (1 if dim == "2d" else 2)
+        assert sol.sweep_layout() == dict(kind=kind, ry=ry, rz=max(rz, 1), ndg=ndg)
         sol.step(inst.nsteps, fixed_inner=sched)
         T, Iq = sol.temperature(), sol.intensity()
     I_ref = np.ascontiguousarray(ref.intensity().transpose(2, 1, 0))
@@ -155,3 +157,19 @@ def test_fp32_reaches_tight_tolerance(gpu, monkeypatch, dim, ry, rz):
         st = sol.step(3)
     print([x["inner"] for x in st], flush=True)
     assert all(x["converged"] and x["inner"] < 100 for x in st)
+
+
+def test_default_layouts(gpu, monkeypatch):
+    """Without overrides: the flattened plane where 64-column tiles would leave
+    lanes idle (4 planes with FP32 storage, 2 with FP64), the column walk where
+    x is a multiple of 64 (2 x 2 with FP64 storage, 1 x 4 with FP32)."""
+    for name in ("BTE_SWEEP_KIND", "BTE_SWEEP_RY", "BTE_SWEEP_RZ", "BTE_SWEEP_NDG"):
+        monkeypatch.delenv(name, raising=False)
+    narrow = case_3d_narrow()
+    full = I.gaussian_3d(64, 6, 5, 2, 8, 3, seed=57, precision=I.PRECISION_FP64, nsteps=1)
+    want = {("narrow", gpu.BTE_FP64): (KIND_FLAT, 0, 2), ("narrow", gpu.BTE_FP32_MIXED): (KIND_FLAT, 0, 4),
+            ("full", gpu.BTE_FP64): (2, 2, 2), ("full", gpu.BTE_FP32_MIXED): (2, 1, 4)}
+    for (which, prec), (kind, ry, rz) in want.items():
+        with gpu.Solver(narrow if which == "narrow" else full, precision=prec) as sol:
+            lay = sol.sweep_layout()
+        assert (lay["kind"], lay["ry"], lay["rz"]) == (kind, ry, rz), (which, prec, lay)
