@@ -4,8 +4,9 @@ Ragged meshes that span two x tiles (the last one partly filled), row and
 plane counts that are not multiples of a block, and a different wall kind on
 each face, so every edge path of the column-walk sweeps (neighbouring tile,
 isothermal table, mirrored direction; first and last rows, planes and lanes)
-is exercised in every layout.  A narrow 3D mesh (13 cells along x) puts
-several rows, and x walls, inside one wave of the flattened-plane layout.
+is exercised in every layout.  Narrow meshes (23 cells along x in 2D, 13 in
+3D) leave most lanes of a column-walk tile idle, and put several rows, and
+x walls, inside one wave of the flattened-plane layout.
 FP64 within 1e-10 relative with the oracle's sweep schedule replayed; FP32
 storage within 1e-5 relative in T.
 """
@@ -54,6 +55,12 @@ def case_2d():
     return mixed_walls(inst, 52)
 
 
+def case_2d_narrow():
+    inst = I.strip_2d(23, 30, 2, 8, 4, seed=58, nsteps=2)
+    inst.name = "layouts2d_23x30"
+    return mixed_walls(inst, 59)
+
+
 def case_3d():
     inst = I.gaussian_3d(70, 11, 7, 2, 8, 3, seed=53, precision=I.PRECISION_FP64, nsteps=2)
     inst.h = [1e-8, 1.2e-8, 0.9e-8]
@@ -68,9 +75,10 @@ def case_3d_narrow():
     return mixed_walls(inst, 56)
 
 
-CASES = {"2d": case_2d, "3d": case_3d, "3dn": case_3d_narrow}
-KIND_WALK, KIND_FLAT = 1, 3  # kernel families (ry = 0: flattened (x, y) plane)
+CASES = {"2d": case_2d, "2dn": case_2d_narrow, "3d": case_3d, "3dn": case_3d_narrow}
+KIND_WALK, KIND_FLAT = 1, 3  # kernel families (ry = 0: flattened (x, y) plane, 3D)
 LAYOUTS = [("2d", 4, 0, 1), ("2d", 8, 0, 3), ("2d", 16, 0, 2),
+           ("2dn", 4, 0, 2), ("2dn", 8, 0, 1),
            ("3d", 2, 2, 1), ("3d", 1, 4, 2), ("3d", 2, 4, 3), ("3d", 0, 4, 1), ("3d", 0, 2, 2),
            ("3dn", 2, 2, 1), ("3dn", 1, 4, 3), ("3dn", 0, 4, 2), ("3dn", 0, 2, 1)]
 
@@ -91,7 +99,7 @@ def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     sched = [s["inner"] for s in ref.run(inst.nsteps)]
     announce(f"{inst.name} ry={ry} rz={rz} ndg={ndg} sched={sched}")
     with gpu.Solver(inst) as sol:
-        kind = KIND_FLAT if ry == 0 else (1 if dim == "2d" else 2)
+        kind = 1 if dim.startswith("2d") else (KIND_FLAT if ry == 0 else 2)
         assert sol.sweep_layout() == dict(kind=kind, ry=ry, rz=max(rz, 1), ndg=ndg)
         sol.step(inst.nsteps, fixed_inner=sched)
         T, Iq = sol.temperature(), sol.intensity()
@@ -102,8 +110,8 @@ def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     assert errT <= 1e-10 and errI <= 1e-10
 
 
-@pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("3d", 1, 4, 2), ("3d", 0, 4, 1),
-                                             ("3dn", 0, 2, 2)])
+@pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("2dn", 4, 0, 1), ("3d", 1, 4, 2),
+                                             ("3d", 0, 4, 1), ("3dn", 0, 2, 2)])
 def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     from oracle import Oracle
     inst = CASES[dim]()
@@ -144,7 +152,8 @@ def test_warm_start_shift_is_layout_independent(gpu, monkeypatch, dim):
         assert err <= 1e-12
 
 
-@pytest.mark.parametrize("dim,ry,rz", [("2d", 4, 0), ("3d", 1, 4), ("3dn", 0, 2), ("3d", 0, 4)])
+@pytest.mark.parametrize("dim,ry,rz", [("2d", 4, 0), ("2dn", 8, 0), ("3d", 1, 4), ("3dn", 0, 2),
+                                       ("3d", 0, 4)])
 def test_fp32_reaches_tight_tolerance(gpu, monkeypatch, dim, ry, rz):
     """With FP32 storage the iterate must settle: the update is rounded once to
     the stored value and the norms use that value, so a converged sweep
