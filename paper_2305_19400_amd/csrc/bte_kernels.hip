@@ -110,14 +110,15 @@ __device__ __forceinline__ Real encode(double iref, double I) {
 
 // Energy sum over a direction group of one (band, cell): sum_d w_d I.  With
 // FP64 storage a plain FP64 sum of the intensities; with FP32 storage a
-// compensated (Neumaier) FP64 sum of the deviations w_d (I - Iref_b), to which
-// Iref_b sum_d w_d is added once at the end.
+// compensated (Kahan) FP64 sum of the deviations w_d (I - Iref_b), to which
+// Iref_b sum_d w_d is added once at the end.  Sc carries the negated rounding
+// error of the running sum.
 template <typename Real>
 __device__ __forceinline__ void accumulate_energy(double& S, double& Sc, double w, double v) {
   if constexpr (Storage<Real>::kDeviation) {
-    const double term = w * v;
-    const double t = S + term;
-    Sc += (fabs(S) >= fabs(term)) ? ((S - t) + term) : ((term - t) + S);
+    const double y = w * v - Sc;
+    const double t = S + y;
+    Sc = (t - S) - y;
     S = t;
   } else {
     S += w * v;
@@ -125,7 +126,7 @@ __device__ __forceinline__ void accumulate_energy(double& S, double& Sc, double 
 }
 template <typename Real>
 __device__ __forceinline__ double energy_partial(double S, double Sc, double iref, double wsum) {
-  if constexpr (Storage<Real>::kDeviation) return iref * wsum + (S + Sc);
+  if constexpr (Storage<Real>::kDeviation) return iref * wsum + (S - Sc);
   else return S;
 }
 
