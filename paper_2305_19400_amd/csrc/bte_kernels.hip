@@ -130,6 +130,33 @@ __device__ __forceinline__ double energy_partial(double S, double Sc, double ire
   else return S;
 }
 
+// The point-Jacobi update of one cell, I_new = I + R / a with
+// R = (I^n - I)/dt + (I0 - I)/tau + sum_in c (I_up - I) and a = 1/dt + 1/tau +
+// sum c.  With FP64 storage it is evaluated in this defect form, which leaves
+// a uniform equilibrium state bit for bit unchanged.  With FP32 storage the
+// equal direct form I_new = (I^n/dt + I0/tau + sum_in c I_up) / a is used on
+// the deviations (fewer operations); its FP64 rounding is far below the single
+// rounding to the stored value.  Each helper is one expression, so FMA
+// contraction is the same wherever it is inlined.
+template <typename Real, typename A>
+__device__ __forceinline__ A update_start(A in, A i0, A v, A inv_dt, A inv_tau) {
+#pragma clang fp contract(on)
+  if constexpr (Storage<Real>::kDeviation) return in * inv_dt + i0 * inv_tau;
+  else return (in - v) * inv_dt + (i0 - v) * inv_tau;
+}
+template <typename Real, typename A>
+__device__ __forceinline__ A update_add(A acc, A c, A up, A v) {
+#pragma clang fp contract(on)
+  if constexpr (Storage<Real>::kDeviation) return acc + c * up;
+  else return acc + c * (up - v);
+}
+template <typename Real, typename A>
+__device__ __forceinline__ Real update_finish(A acc, A v, A scale) {
+#pragma clang fp contract(on)
+  if constexpr (Storage<Real>::kDeviation) return static_cast<Real>(acc * scale);
+  else return static_cast<Real>(v + acc * scale);
+}
+
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
@@ -544,24 +571,24 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
       const A exj = read_lane(ex, j);
       if (colok && j < nrows) {
         const A v = ik[j];
-        A acc = (in[j] - v) * a_inv_dt + (I0r[j] - v) * a_inv_tau;
+        A acc = update_start<Real>(in[j], I0r[j], v, a_inv_dt, a_inv_tau);
         if (xpos) {
           const A up = lane == 0 ? exj : nbr;
-          acc += c0 * (up - v);
+          acc = update_add<Real>(acc, c0, up, v);
         } else if (xneg) {
           const A up = lane == last ? exj : nbr;
-          acc += c0 * (up - v);
+          acc = update_add<Real>(acc, c0, up, v);
         }
         if (ypos) {
           const A up = (j == 0) ? ey : ik[j > 0 ? j - 1 : 0];
-          acc += c1 * (up - v);
+          acc = update_add<Real>(acc, c1, up, v);
         } else if (yneg) {
           const A up = (j == nrows - 1) ? ey : ik[j + 1 < RY ? j + 1 : RY - 1];
-          acc += c1 * (up - v);
+          acc = update_add<Real>(acc, c1, up, v);
         }
         // the stored value drives the norms and the energy: once the
         // iterate stops changing in storage precision its increment is zero
-        const Real inew_r = static_cast<Real>(v + acc * scale);
+        const Real inew_r = update_finish<Real>(acc, v, scale);
         buf_store<Real>(inew_r, ro, vrow[j], 0);
         const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
@@ -840,31 +867,31 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
         const A exjk = read_lane(ex, j + RY * k);
         if (colok && j < nrows && k < nplanes) {
           const A v = ik[j][k];
-          A acc = (in[j][k] - v) * a_inv_dt + (I0r[j][k] - v) * a_inv_tau;
+          A acc = update_start<Real>(in[j][k], I0r[j][k], v, a_inv_dt, a_inv_tau);
           if (xpos) {
             const A up = lane == 0 ? exjk : nbr;
-            acc += c0 * (up - v);
+            acc = update_add<Real>(acc, c0, up, v);
           } else if (xneg) {
             const A up = lane == last ? exjk : nbr;
-            acc += c0 * (up - v);
+            acc = update_add<Real>(acc, c0, up, v);
           }
           if (ypos) {
             const A up = (j == 0) ? ey[k] : ik[j > 0 ? j - 1 : 0][k];
-            acc += c1 * (up - v);
+            acc = update_add<Real>(acc, c1, up, v);
           } else if (yneg) {
             const A up = (j == nrows - 1) ? ey[k] : ik[j + 1 < RY ? j + 1 : RY - 1][k];
-            acc += c1 * (up - v);
+            acc = update_add<Real>(acc, c1, up, v);
           }
           if (zpos) {
             const A up = (k == 0) ? ez[j] : ik[j][k > 0 ? k - 1 : 0];
-            acc += c2 * (up - v);
+            acc = update_add<Real>(acc, c2, up, v);
           } else if (zneg) {
             const A up = (k == nplanes - 1) ? ez[j] : ik[j][k + 1 < RZ ? k + 1 : RZ - 1];
-            acc += c2 * (up - v);
+            acc = update_add<Real>(acc, c2, up, v);
           }
           // the stored value drives the norms and the energy: once the
           // iterate stops changing in storage precision its increment is zero
-          const Real inew_r = static_cast<Real>(v + acc * scale);
+          const Real inew_r = update_finish<Real>(acc, v, scale);
           buf_store<Real>(inew_r, ro, vc[j][k], 0);
           const A inew = inew_r;
           const double da = static_cast<double>(inew - v);
@@ -1107,25 +1134,25 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
       if constexpr (SHIFT) ey += ypos ? shy_p[k] : shy_n[k];
       if (fok && k < nplanes) {
         const A v = ik[k];
-        A acc = (in[k] - v) * a_inv_dt + (I0r[k] - v) * a_inv_tau;
+        A acc = update_start<Real>(in[k], I0r[k], v, a_inv_dt, a_inv_tau);
         if (xpos || xneg) {
           const A up = xw ? xg[k] : (lane == edge_lane ? exk : nbr);
-          acc += c0 * (up - v);
+          acc = update_add<Real>(acc, c0, up, v);
         }
         if (ypos || yneg) {
           const A up = yw ? yg[k] : ey;
-          acc += c1 * (up - v);
+          acc = update_add<Real>(acc, c1, up, v);
         }
         if (zpos) {
           const A up = (k == 0) ? ez : ik[k > 0 ? k - 1 : 0];
-          acc += c2 * (up - v);
+          acc = update_add<Real>(acc, c2, up, v);
         } else if (zneg) {
           const A up = (k == nplanes - 1) ? ez : ik[k + 1 < RZ ? k + 1 : RZ - 1];
-          acc += c2 * (up - v);
+          acc = update_add<Real>(acc, c2, up, v);
         }
         // the stored value drives the norms and the energy: once the
         // iterate stops changing in storage precision its increment is zero
-        const Real inew_r = static_cast<Real>(v + acc * scale);
+        const Real inew_r = update_finish<Real>(acc, v, scale);
         buf_store<Real>(inew_r, ro, vc[k], 0);
         const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
