@@ -277,6 +277,13 @@ struct bte_ctx {
   int nn_warm_steps, nn_warm_sweeps;  // warm-started steps so far and their sweeps
   std::vector<int> nn_plain_sweeps;   // sweeps of the recorded plain steps
   int nn_adam_t;    // Adam steps taken
+  // Set by a batch step: training is enqueued on this stream, after the work
+  // already on the context's stream, and its loss is read after the batch
+  // joins the stream (null: train on the context's stream and wait).
+  hipStream_t train_stream = nullptr;
+  hipEvent_t train_fork = nullptr;  // created on first deferred training
+  bool nn_loss_pending = false;
+  int nn_last_batch = 1;            // samples of the last minibatch
   bool poisoned;
 };
 
@@ -364,10 +371,29 @@ long long gcd_ll(long long a, long long b) {
 // Adam over minibatches in a pseudo-random sample order (affine permutation
 // i -> (a i + c) mod N with gcd(a, N) = 1), at least two passes and 300 updates
 // unless nn_epochs is given.
+// Mean loss over the last minibatch of the last training (waits for it).
+int nn_read_loss(bte_ctx* ctx, double* last_loss) {
+  float loss = 0.f;
+  HIP_TRY(hipMemcpyAsync(&loss, ctx->nnB.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (last_loss) *last_loss = (double)loss / (double)ctx->nn_last_batch;
+  ctx->nn_loss_pending = false;
+  return BTE_OK;
+}
+
 int nn_train(bte_ctx* ctx, double* last_loss) {
   const int nc = ctx->s.nc;
   const long long N = (long long)ctx->nn_nrec * nc;
-  HIP_TRY(nn_stats(ctx->stream, ctx->nnL, ctx->nnB, ctx->nn_nrec, nc));
+  hipStream_t s = ctx->stream;
+  if (ctx->train_stream) {
+    // after everything already enqueued for this context (the samples)
+    if (!ctx->train_fork)
+      HIP_TRY(hipEventCreateWithFlags(&ctx->train_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ctx->train_fork, ctx->stream));
+    HIP_TRY(hipStreamWaitEvent(ctx->train_stream, ctx->train_fork, 0));
+    s = ctx->train_stream;
+  }
+  HIP_TRY(nn_stats(s, ctx->nnL, ctx->nnB, ctx->nn_nrec, nc));
   long long a = (long long)(0.6180339887 * (double)N) | 1;
   while (gcd_ll(a, N) != 1) a += 2;
   const long long per_epoch = (N + kNnBatch - 1) / kNnBatch;
@@ -380,16 +406,18 @@ int nn_train(bte_ctx* ctx, double* last_loss) {
     for (long long b0 = 0; b0 < N; b0 += kNnBatch) {
       batch = (int)std::min<long long>(kNnBatch, N - b0);
       ctx->nn_adam_t += 1;
-      HIP_TRY(nn_train_batch(ctx->stream, ctx->g, ctx->nnL, ctx->nnB, N, a, c, b0, batch, lr,
+      HIP_TRY(nn_train_batch(s, ctx->g, ctx->nnL, ctx->nnB, N, a, c, b0, batch, lr,
                              ctx->nn_adam_t, true));
     }
   }
-  float loss = 0.f;
-  HIP_TRY(hipMemcpyAsync(&loss, ctx->nnB.loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
-  if (last_loss) *last_loss = (double)loss / (double)batch;  // mean over the last minibatch
+  ctx->nn_last_batch = batch;
   ctx->nn_ready = 1;
-  return BTE_OK;
+  if (ctx->train_stream) {  // the batch joins the stream and reads the loss
+    ctx->nn_loss_pending = true;
+    if (last_loss) *last_loss = 0.0;
+    return BTE_OK;
+  }
+  return nn_read_loss(ctx, last_loss);
 }
 
 // What one time step decided before its inner loop.
@@ -1001,6 +1029,7 @@ int bte_destroy(bte_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ring_ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->train_fork) (void)hipEventDestroy(ctx->train_fork);
   for (auto e : ctx->t_start) (void)hipEventDestroy(e);
   for (auto e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->host_ring) (void)hipHostFree(ctx->host_ring);
@@ -1154,6 +1183,10 @@ struct bte_batch {
   BatchControl* h_bc;  // pinned
   Control* h_ctl;      // pinned, one per geometry
   int sweep_blocks[kBatchLists];
+  // side streams on which the networks of several geometries train at once
+  static constexpr int kTrainStreams = 4;
+  hipStream_t train[kTrainStreams];
+  hipEvent_t train_done[kTrainStreams];
   int temp_blocks;
   int max_inner;
   bool use_graph;
@@ -1220,6 +1253,10 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   b->graph = nullptr;
   b->exec = nullptr;
   for (auto& e : b->ev) e = nullptr;
+  for (int k = 0; k < bte_batch::kTrainStreams; ++k) {
+    b->train[k] = nullptr;
+    b->train_done[k] = nullptr;
+  }
   b->max_inner = 0;
   // work lists (2D; 3D; 3D flattened plane with 4 planes), each ordered
   // largest geometry first
@@ -1278,6 +1315,10 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   BATCH_TRY(hipHostMalloc((void**)&b->h_bc, sizeof(BatchControl)));
   BATCH_TRY(hipHostMalloc((void**)&b->h_ctl, sizeof(Control) * n));
   for (auto& e : b->ev) BATCH_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (int k = 0; k < bte_batch::kTrainStreams; ++k) {  // default priority
+    BATCH_TRY(hipStreamCreateWithFlags(&b->train[k], hipStreamNonBlocking));
+    BATCH_TRY(hipEventCreateWithFlags(&b->train_done[k], hipEventDisableTiming));
+  }
   if (!items.empty())
     BATCH_TRY(hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
                              hipMemcpyHostToDevice, b->stream));
@@ -1371,11 +1412,28 @@ int bte_batch_step(bte_batch* b, int nsteps, bte_step_stats* stats) {
       HIP_TRY(hipMemcpyAsync(&b->h_ctl[i], b->ctx[i]->ctl, sizeof(Control), hipMemcpyDeviceToHost,
                              b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    for (int i = 0; i < n; ++i) {
+    // Geometries whose training falls due in this step train concurrently,
+    // on the side streams (each in its own order, so results do not change);
+    // the batch stream waits for all of them before the next step.
+    for (int i = 0; i < n; ++i) b->ctx[i]->train_stream = b->train[i % bte_batch::kTrainStreams];
+    int rc = BTE_OK;
+    for (int i = 0; i < n && rc == BTE_OK; ++i) {
       const Control fin = b->h_ctl[i];
-      int rc = step_finish(b->ctx[i], ss[i], fin, stats ? &stats[(size_t)step * n + i] : nullptr);
-      if (rc != BTE_OK) return rc;
+      rc = step_finish(b->ctx[i], ss[i], fin, stats ? &stats[(size_t)step * n + i] : nullptr);
     }
+    for (int i = 0; i < n; ++i) b->ctx[i]->train_stream = nullptr;
+    for (int k = 0; k < bte_batch::kTrainStreams; ++k) {
+      HIP_TRY(hipEventRecord(b->train_done[k], b->train[k]));
+      HIP_TRY(hipStreamWaitEvent(b->stream, b->train_done[k], 0));
+    }
+    if (rc != BTE_OK) return rc;
+    for (int i = 0; i < n; ++i)
+      if (b->ctx[i]->nn_loss_pending) {
+        double loss = 0.0;
+        const int lrc = nn_read_loss(b->ctx[i], &loss);
+        if (lrc != BTE_OK) return lrc;
+        if (stats) stats[(size_t)step * n + i].nn_loss = loss;
+      }
   }
   return BTE_OK;
 }
@@ -1387,6 +1445,10 @@ int bte_batch_destroy(bte_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto e : b->ev)
     if (e) (void)hipEventDestroy(e);
+  for (int k = 0; k < bte_batch::kTrainStreams; ++k) {
+    if (b->train_done[k]) (void)hipEventDestroy(b->train_done[k]);
+    if (b->train[k]) (void)hipStreamDestroy(b->train[k]);
+  }
   if (b->d_ctx) (void)hipFree(b->d_ctx);
   if (b->h_ctx) (void)hipHostFree(b->h_ctx);
   if (b->d_items) (void)hipFree(b->d_items);
