@@ -1353,6 +1353,7 @@ __device__ __forceinline__ void relation_part(const Tables& t, int nb, int l, do
                                               double& dF) {
 #pragma clang fp contract(off)
   double f = 0.0, df = 0.0;
+#pragma unroll 4
   for (int b = l; b < nb; b += kLanesPerCell) {
     const double x = t.xfac[b] / T;
     const double em1 = expm1(x);
@@ -1381,11 +1382,32 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
   const size_t ncp = (size_t)g.ncp;
   CompSum Gs, Es;
   if (active) {
-    for (int b = l; b < g.nb; b += kLanesPerCell) {
-      CompSum s;
-      for (int q = 0; q < g.ndg; ++q) s.add(S[((size_t)q * g.nb + b) * ncp + Pc]);
-      Gs.add(t.fweight[b] * s.value());
-      Es.add(s.value());
+    // The partials of up to kChunk of this lane's bands are requested
+    // together for each direction group, so their loads are in flight at
+    // once; each band still sums its groups in order, and the bands enter
+    // G and E in order.
+    constexpr int kChunk = 4;
+    const size_t qstride = (size_t)g.nb * ncp;
+    for (int b0 = l; b0 < g.nb; b0 += kLanesPerCell * kChunk) {
+      CompSum s[kChunk];
+      for (int q = 0; q < g.ndg; ++q) {
+        double v[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+          const int b = b0 + i * kLanesPerCell;
+          v[i] = b < g.nb ? S[(size_t)q * qstride + (size_t)b * ncp + Pc] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) s[i].add(v[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) {
+        const int b = b0 + i * kLanesPerCell;
+        if (b < g.nb) {
+          Gs.add(t.fweight[b] * s[i].value());
+          Es.add(s[i].value());
+        }
+      }
     }
   }
   const double Gp = Gs.value(), Ep = Es.value();
@@ -1419,6 +1441,7 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
     if (l == 0) atomicMin(&ctl->err_cell, P);
     return;
   }
+#pragma unroll 4
   for (int b = l; b < g.nb; b += kLanesPerCell)
     I0[(size_t)b * ncp + P] = equilibrium(t.Cb[b], t.xfac[b], Tc);
   if (l == 0) {
@@ -1738,8 +1761,17 @@ __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx
 __global__ __launch_bounds__(256) void batch_temperature_kernel(const BatchCtx* __restrict__ ctxs,
                                                                 int nctx) {
   const int blk = blockIdx.x;
-  int ci = 0;
-  while (ci + 1 < nctx && blk >= ctxs[ci + 1].cell_block0) ++ci;
+  // the context of this block: the number of contexts whose first block is
+  // at or before it, less one (first blocks ascend), counted 64 at a time
+  // by a ballot over the lanes instead of a chain of dependent loads
+  int ci = -1;
+  for (int c0 = 0; c0 < nctx; c0 += 64) {
+    const int j = c0 + (int)(threadIdx.x & 63);
+    const unsigned long long m = __ballot(j < nctx && ctxs[j].cell_block0 <= blk);
+    ci += __popcll(m);
+    if (m != ~0ull) break;
+  }
+  ci = __builtin_amdgcn_readfirstlane(max(ci, 0));
   const BatchCtx& c = ctxs[ci];
   if (blk - c.cell_block0 >= c.cell_blocks || step_done(c.ctl)) return;
   temperature_body(c.sp64.g, c.sp64.t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
