@@ -277,12 +277,11 @@ struct bte_ctx {
   int nn_warm_steps, nn_warm_sweeps;  // warm-started steps so far and their sweeps
   std::vector<int> nn_plain_sweeps;   // sweeps of the recorded plain steps
   int nn_adam_t;    // Adam steps taken
-  // Set by a batch step: training is enqueued on this stream, after the work
-  // already on the context's stream, and its loss is read after the batch
-  // joins the stream (null: train on the context's stream and wait).
-  hipStream_t train_stream = nullptr;
-  hipEvent_t train_fork = nullptr;  // created on first deferred training
-  bool nn_loss_pending = false;
+  // Set by a batch step: a training that falls due is queued here and run,
+  // together with the other geometries' trainings, by the batch (null: train
+  // at once).
+  std::vector<bte_ctx*>* train_queue = nullptr;
+  bool nn_loss_pending = false;     // trained; loss not read yet
   int nn_last_batch = 1;            // samples of the last minibatch
   bool poisoned;
 };
@@ -367,10 +366,6 @@ long long gcd_ll(long long a, long long b) {
   return a;
 }
 
-// Trains the network on the recorded steps: normalisation constants, then
-// Adam over minibatches in a pseudo-random sample order (affine permutation
-// i -> (a i + c) mod N with gcd(a, N) = 1), at least two passes and 300 updates
-// unless nn_epochs is given.
 // Mean loss over the last minibatch of the last training (waits for it).
 int nn_read_loss(bte_ctx* ctx, double* last_loss) {
   float loss = 0.f;
@@ -381,42 +376,55 @@ int nn_read_loss(bte_ctx* ctx, double* last_loss) {
   return BTE_OK;
 }
 
-int nn_train(bte_ctx* ctx, double* last_loss) {
-  const int nc = ctx->s.nc;
-  const long long N = (long long)ctx->nn_nrec * nc;
-  hipStream_t s = ctx->stream;
-  if (ctx->train_stream) {
-    // after everything already enqueued for this context (the samples)
-    if (!ctx->train_fork)
-      HIP_TRY(hipEventCreateWithFlags(&ctx->train_fork, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(ctx->train_fork, ctx->stream));
-    HIP_TRY(hipStreamWaitEvent(ctx->train_stream, ctx->train_fork, 0));
-    s = ctx->train_stream;
-  }
-  HIP_TRY(nn_stats(s, ctx->nnL, ctx->nnB, ctx->nn_nrec, nc));
-  long long a = (long long)(0.6180339887 * (double)N) | 1;
-  while (gcd_ll(a, N) != 1) a += 2;
+// The minibatch schedule of a training: Adam over minibatches in a
+// pseudo-random sample order (affine permutation i -> (a i + c_e) mod N with
+// gcd(a, N) = 1, c_e per epoch), at least two passes and 300 updates unless
+// nn_epochs is given.
+struct TrainSchedule {
+  long long N, a;
+  float lr;
+  struct Update {
+    long long b0, c;
+    int batch;
+  };
+  std::vector<Update> updates;
+};
+
+TrainSchedule nn_schedule(const bte_ctx* ctx) {
+  TrainSchedule ts;
+  ts.N = (long long)ctx->nn_nrec * ctx->s.nc;
+  const long long N = ts.N;
+  ts.a = (long long)(0.6180339887 * (double)N) | 1;
+  while (gcd_ll(ts.a, N) != 1) ts.a += 2;
   const long long per_epoch = (N + kNnBatch - 1) / kNnBatch;
   int epochs = ctx->opt.nn_epochs;
   if (epochs <= 0) epochs = (int)std::max<long long>(2, (300 + per_epoch - 1) / per_epoch);
-  const float lr = ctx->opt.nn_lr > 0.f ? ctx->opt.nn_lr : 1e-3f;
-  int batch = 1;
+  ts.lr = ctx->opt.nn_lr > 0.f ? ctx->opt.nn_lr : 1e-3f;
   for (int e = 0; e < epochs; ++e) {
     const long long c = ((long long)e * 7919) % N;
-    for (long long b0 = 0; b0 < N; b0 += kNnBatch) {
-      batch = (int)std::min<long long>(kNnBatch, N - b0);
-      ctx->nn_adam_t += 1;
-      HIP_TRY(nn_train_batch(s, ctx->g, ctx->nnL, ctx->nnB, N, a, c, b0, batch, lr,
-                             ctx->nn_adam_t, true));
-    }
+    for (long long b0 = 0; b0 < N; b0 += kNnBatch)
+      ts.updates.push_back({b0, c, (int)std::min<long long>(kNnBatch, N - b0)});
   }
-  ctx->nn_last_batch = batch;
-  ctx->nn_ready = 1;
-  if (ctx->train_stream) {  // the batch joins the stream and reads the loss
-    ctx->nn_loss_pending = true;
+  return ts;
+}
+
+// Trains the network on the recorded steps: normalisation constants, then the
+// minibatch schedule above (or queues the context for its batch to train).
+int nn_train(bte_ctx* ctx, double* last_loss) {
+  if (ctx->train_queue) {  // the batch trains it with the others
+    ctx->train_queue->push_back(ctx);
     if (last_loss) *last_loss = 0.0;
     return BTE_OK;
   }
+  HIP_TRY(nn_stats(ctx->stream, ctx->nnL, ctx->nnB, ctx->nn_nrec, ctx->s.nc));
+  const TrainSchedule ts = nn_schedule(ctx);
+  for (const auto& u : ts.updates) {
+    ctx->nn_adam_t += 1;
+    HIP_TRY(nn_train_batch(ctx->stream, ctx->g, ctx->nnL, ctx->nnB, ts.N, ts.a, u.c, u.b0,
+                           u.batch, ts.lr, ctx->nn_adam_t, true));
+  }
+  ctx->nn_last_batch = ts.updates.back().batch;
+  ctx->nn_ready = 1;
   return nn_read_loss(ctx, last_loss);
 }
 
@@ -1029,7 +1037,6 @@ int bte_destroy(bte_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ring_ev)
     if (e) (void)hipEventDestroy(e);
-  if (ctx->train_fork) (void)hipEventDestroy(ctx->train_fork);
   for (auto e : ctx->t_start) (void)hipEventDestroy(e);
   for (auto e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->host_ring) (void)hipHostFree(ctx->host_ring);
@@ -1183,10 +1190,11 @@ struct bte_batch {
   BatchControl* h_bc;  // pinned
   Control* h_ctl;      // pinned, one per geometry
   int sweep_blocks[kBatchLists];
-  // side streams on which the networks of several geometries train at once
-  static constexpr int kTrainStreams = 4;
-  hipStream_t train[kTrainStreams];
-  hipEvent_t train_done[kTrainStreams];
+  // trainings of several geometries run together: jobs and per-iteration
+  // minibatches in device memory (grown on demand)
+  NnTrainJob* d_jobs;
+  NnTrainStep* d_steps;
+  size_t jobs_cap, steps_cap;
   int temp_blocks;
   int max_inner;
   bool use_graph;
@@ -1253,10 +1261,9 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   b->graph = nullptr;
   b->exec = nullptr;
   for (auto& e : b->ev) e = nullptr;
-  for (int k = 0; k < bte_batch::kTrainStreams; ++k) {
-    b->train[k] = nullptr;
-    b->train_done[k] = nullptr;
-  }
+  b->d_jobs = nullptr;
+  b->d_steps = nullptr;
+  b->jobs_cap = b->steps_cap = 0;
   b->max_inner = 0;
   // work lists (2D; 3D; 3D flattened plane with 4 planes), each ordered
   // largest geometry first
@@ -1315,10 +1322,6 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   BATCH_TRY(hipHostMalloc((void**)&b->h_bc, sizeof(BatchControl)));
   BATCH_TRY(hipHostMalloc((void**)&b->h_ctl, sizeof(Control) * n));
   for (auto& e : b->ev) BATCH_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  for (int k = 0; k < bte_batch::kTrainStreams; ++k) {  // default priority
-    BATCH_TRY(hipStreamCreateWithFlags(&b->train[k], hipStreamNonBlocking));
-    BATCH_TRY(hipEventCreateWithFlags(&b->train_done[k], hipEventDisableTiming));
-  }
   if (!items.empty())
     BATCH_TRY(hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
                              hipMemcpyHostToDevice, b->stream));
@@ -1340,6 +1343,63 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   }
 #undef BATCH_TRY
   *out = b;
+  (void)ctx;
+  return BTE_OK;
+}
+
+// Trains the networks of the queued geometries together: normalisation
+// constants of each, then one launch per kernel and iteration for all of
+// them, each following its own minibatch schedule.
+static int batch_train(bte_batch* b, const std::vector<bte_ctx*>& due) {
+  bte_ctx* ctx = due.front();
+  const int nj = (int)due.size();
+  std::vector<TrainSchedule> ts(nj);
+  std::vector<NnTrainJob> jobs(nj);
+  size_t niters = 0;
+  int max_kp = 0;
+  for (int j = 0; j < nj; ++j) {
+    bte_ctx* c = due[j];
+    HIP_TRY(nn_stats(b->stream, c->nnL, c->nnB, c->nn_nrec, c->s.nc));
+    ts[j] = nn_schedule(c);
+    jobs[j] = NnTrainJob{c->g, c->nnL, c->nnB, ts[j].N, ts[j].a, ts[j].lr};
+    niters = std::max(niters, ts[j].updates.size());
+    max_kp = std::max(max_kp, c->nnL.KP);
+  }
+  std::vector<NnTrainStep> steps(niters * nj, NnTrainStep{0, 0, 0, 0, 1.f, 1.f});
+  for (int j = 0; j < nj; ++j)
+    for (size_t it = 0; it < ts[j].updates.size(); ++it) {
+      const auto& u = ts[j].updates[it];
+      const int t = due[j]->nn_adam_t + (int)it + 1;  // Adam step number of this update
+      steps[it * nj + j] = NnTrainStep{u.b0, u.c, u.batch, 1, 1.f - powf(0.9f, (float)t),
+                                       1.f - powf(0.999f, (float)t)};
+    }
+  if (jobs.size() > b->jobs_cap) {
+    if (b->d_jobs) HIP_TRY(hipFree(b->d_jobs));
+    b->d_jobs = nullptr;
+    HIP_TRY(hipMalloc((void**)&b->d_jobs, sizeof(NnTrainJob) * jobs.size()));
+    b->jobs_cap = jobs.size();
+  }
+  if (steps.size() > b->steps_cap) {
+    if (b->d_steps) HIP_TRY(hipFree(b->d_steps));
+    b->d_steps = nullptr;
+    HIP_TRY(hipMalloc((void**)&b->d_steps, sizeof(NnTrainStep) * steps.size()));
+    b->steps_cap = steps.size();
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(NnTrainJob) * jobs.size(),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_steps, steps.data(), sizeof(NnTrainStep) * steps.size(),
+                         hipMemcpyHostToDevice, b->stream));
+  for (size_t it = 0; it < niters; ++it)
+    HIP_TRY(nn_train_many(b->stream, b->d_jobs, b->d_steps, nj, (int)it, max_kp));
+  // the host vectors are read by the copies above: wait before they go
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int j = 0; j < nj; ++j) {
+    bte_ctx* c = due[j];
+    c->nn_adam_t += (int)ts[j].updates.size();
+    c->nn_last_batch = ts[j].updates.back().batch;
+    c->nn_ready = 1;
+    c->nn_loss_pending = true;
+  }
   (void)ctx;
   return BTE_OK;
 }
@@ -1412,21 +1472,22 @@ int bte_batch_step(bte_batch* b, int nsteps, bte_step_stats* stats) {
       HIP_TRY(hipMemcpyAsync(&b->h_ctl[i], b->ctx[i]->ctl, sizeof(Control), hipMemcpyDeviceToHost,
                              b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    // Geometries whose training falls due in this step train concurrently,
-    // on the side streams (each in its own order, so results do not change);
-    // the batch stream waits for all of them before the next step.
-    for (int i = 0; i < n; ++i) b->ctx[i]->train_stream = b->train[i % bte_batch::kTrainStreams];
+    // The geometries whose training falls due in this step are queued and
+    // trained together (each on its own samples, in its own order, so the
+    // results are those of training it alone).
+    std::vector<bte_ctx*> due;
+    for (int i = 0; i < n; ++i) b->ctx[i]->train_queue = &due;
     int rc = BTE_OK;
     for (int i = 0; i < n && rc == BTE_OK; ++i) {
       const Control fin = b->h_ctl[i];
       rc = step_finish(b->ctx[i], ss[i], fin, stats ? &stats[(size_t)step * n + i] : nullptr);
     }
-    for (int i = 0; i < n; ++i) b->ctx[i]->train_stream = nullptr;
-    for (int k = 0; k < bte_batch::kTrainStreams; ++k) {
-      HIP_TRY(hipEventRecord(b->train_done[k], b->train[k]));
-      HIP_TRY(hipStreamWaitEvent(b->stream, b->train_done[k], 0));
-    }
+    for (int i = 0; i < n; ++i) b->ctx[i]->train_queue = nullptr;
     if (rc != BTE_OK) return rc;
+    if (!due.empty()) {
+      rc = batch_train(b, due);
+      if (rc != BTE_OK) return rc;
+    }
     for (int i = 0; i < n; ++i)
       if (b->ctx[i]->nn_loss_pending) {
         double loss = 0.0;
@@ -1445,10 +1506,8 @@ int bte_batch_destroy(bte_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto e : b->ev)
     if (e) (void)hipEventDestroy(e);
-  for (int k = 0; k < bte_batch::kTrainStreams; ++k) {
-    if (b->train_done[k]) (void)hipEventDestroy(b->train_done[k]);
-    if (b->train[k]) (void)hipStreamDestroy(b->train[k]);
-  }
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_steps) (void)hipFree(b->d_steps);
   if (b->d_ctx) (void)hipFree(b->d_ctx);
   if (b->h_ctx) (void)hipHostFree(b->h_ctx);
   if (b->d_items) (void)hipFree(b->d_items);

@@ -61,6 +61,25 @@ struct NnBuffers {
   NnScratch scr;
 };
 
+// Training of several networks at once (the geometries of a batch).
+struct NnTrainJob {
+  Geometry g;
+  NnLayout L;
+  NnBuffers B;
+  long long nsamples, perm_a;  // recorded samples and the sample-order multiplier
+  float lr;
+};
+// One network's minibatch of one iteration (active = 0: its schedule has ended).
+struct NnTrainStep {
+  long long batch0, perm_c;
+  int batch, active;
+  float b1c, b2c;  // Adam bias corrections of this update
+};
+// Iteration it of every job (jobs and steps in device memory, steps[it][job]);
+// max_kp bounds the jobs' padded feature counts.
+hipError_t nn_train_many(hipStream_t s, const NnTrainJob* jobs, const NnTrainStep* steps,
+                         int njobs, int it, int max_kp);
+
 hipError_t nn_init(hipStream_t s, const NnLayout& L, const NnBuffers& B, unsigned long long seed);
 hipError_t nn_refresh(hipStream_t s, const NnLayout& L, const NnBuffers& B);
 hipError_t nn_record(hipStream_t s, int nc, const double* T, const double* Tp, const double* E,

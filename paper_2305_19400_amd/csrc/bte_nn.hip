@@ -83,16 +83,17 @@ __device__ __forceinline__ double field_value(const FieldSource& src, int ch, lo
   return ch == 0 ? src.T[Q] : (ch == 1 ? src.Tp[Q] : src.E[Q]);
 }
 
-// One workgroup = 4 waves x 16 samples.  TRAIN also back-propagates and writes
-// the transposed activations / pre-activation gradients of its samples for the
-// weight-gradient products, plus per-workgroup partial sums of the bias and
-// output-weight gradients and of the loss.
+// One workgroup (number bx) = 4 waves x 16 samples.  TRAIN also
+// back-propagates and writes the transposed activations / pre-activation
+// gradients of its samples for the weight-gradient products, plus
+// per-workgroup partial sums of the bias and output-weight gradients and of
+// the loss.
 template <bool TRAIN>
-__global__ __launch_bounds__(256) void mlp_kernel(Geometry g, NnLayout L, const float* params,
-                                                  const unsigned short* W1b,
-                                                  const unsigned short* W2b,
-                                                  const unsigned short* W2Tb, FieldSource src,
-                                                  float* yout, NnScratch scr) {
+__device__ __forceinline__ void mlp_body(const Geometry& g, const NnLayout& L,
+                                         const float* params, const unsigned short* W1b,
+                                         const unsigned short* W2b, const unsigned short* W2Tb,
+                                         const FieldSource& src, float* yout,
+                                         const NnScratch& scr, const int bx) {
   __shared__ __attribute__((aligned(16))) unsigned short xs[4][16][kNnMaxK + 8];
   __shared__ __attribute__((aligned(16))) unsigned short hs[4][16][kNnHidden + 8];
   __shared__ __attribute__((aligned(16))) unsigned short ds[4][16][kNnHidden + 8];
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void mlp_kernel(Geometry g, NnLayout L, const 
   const int w = threadIdx.x >> 6;
   const int K = L.K, KP = L.KP;
   const int nc = g.nc;
-  const int r0 = (blockIdx.x * 4 + w) * 16;  // first sample (minibatch position) of this wave
+  const int r0 = (bx * 4 + w) * 16;  // first sample (minibatch position) of this wave
   const int nsamp = TRAIN ? src.batch : nc;
   const Norm nm = read_norm(params, L);
   const int S = (g.dim == 3) ? 27 : 9;
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void mlp_kernel(Geometry g, NnLayout L, const 
   }
   __syncthreads();
   // per-workgroup partials, waves summed in a fixed order
-  float* part = scr.part + (size_t)blockIdx.x * kNnPartWidth;
+  float* part = scr.part + (size_t)bx * kNnPartWidth;
   if (threadIdx.x < kNnHidden) {
     const int n = threadIdx.x;
     for (int q = 0; q < 3; ++q) {
@@ -301,13 +302,23 @@ __global__ __launch_bounds__(256) void mlp_kernel(Geometry g, NnLayout L, const 
   }
 }
 
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void mlp_kernel(Geometry g, NnLayout L, const float* params,
+                                                  const unsigned short* W1b,
+                                                  const unsigned short* W2b,
+                                                  const unsigned short* W2Tb, FieldSource src,
+                                                  float* yout, NnScratch scr) {
+  mlp_body<TRAIN>(g, L, params, W1b, W2b, W2Tb, src, yout, scr, blockIdx.x);
+}
+
 // dW = dZ^T A over the minibatch: one wave per 16x16 tile of dW1 (128 x KP) or
 // dW2 (128 x 128), samples in a fixed order.
-__global__ __launch_bounds__(64) void wgrad_kernel(NnLayout L, NnScratch scr, float* grad) {
+__device__ __forceinline__ int wgrad_tiles(const NnLayout& L) { return 8 * (L.KP / 16) + 64; }
+__device__ __forceinline__ void wgrad_body(const NnLayout& L, const NnScratch& scr, float* grad,
+                                           int tile) {
   const int lane = threadIdx.x;
   const int col = lane & 15, grp = lane >> 4;
   const int t1 = 8 * (L.KP / 16);
-  int tile = blockIdx.x;
   const unsigned short* dZT;
   const unsigned short* AT;
   int kdim;
@@ -335,10 +346,14 @@ __global__ __launch_bounds__(64) void wgrad_kernel(NnLayout L, NnScratch scr, fl
   for (int i = 0; i < 4; ++i)
     grad[base + (size_t)(16 * tn + 4 * grp + i) * kdim + 16 * tk + col] = acc[i];
 }
+__global__ __launch_bounds__(64) void wgrad_kernel(NnLayout L, NnScratch scr, float* grad) {
+  wgrad_body(L, scr, grad, blockIdx.x);
+}
 
 // Bias / output-weight gradients and the loss: partials of all workgroups
 // summed in a fixed order.
-__global__ void bias_grad_kernel(NnLayout L, NnScratch scr, int nwg, float* grad, float* loss) {
+__device__ __forceinline__ void bias_grad_body(const NnLayout& L, const NnScratch& scr, int nwg,
+                                               float* grad, float* loss) {
   const int j = threadIdx.x;
   if (j >= kNnPartWidth) return;
   float s = 0.f;
@@ -349,13 +364,17 @@ __global__ void bias_grad_kernel(NnLayout L, NnScratch scr, int nwg, float* grad
   else if (j == 3 * kNnHidden) grad[L.o_b3] = s;
   else if (j == 3 * kNnHidden + 1 && loss) *loss = s;
 }
+__global__ void bias_grad_kernel(NnLayout L, NnScratch scr, int nwg, float* grad, float* loss) {
+  bias_grad_body(L, scr, nwg, grad, loss);
+}
 
 // Adam step on every trainable parameter (padded feature columns stay zero),
 // then refresh the bf16 operand copies.
-__global__ void adam_kernel(NnLayout L, float* params, const float* grad, float* m, float* v,
-                            float lr, float b1c, float b2c, unsigned short* W1b,
-                            unsigned short* W2b, unsigned short* W2Tb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adam_body(const NnLayout& L, float* params, const float* grad,
+                                          float* m, float* v, float lr, float b1c, float b2c,
+                                          unsigned short* W1b, unsigned short* W2b,
+                                          unsigned short* W2Tb, int bx) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= L.o_norm) return;
   const bool pad_col = (i < L.o_b1) && ((i % L.KP) >= L.K);
   const bool b3pad = (i > L.o_b3 && i < L.o_b3 + 4);
@@ -375,6 +394,11 @@ __global__ void adam_kernel(NnLayout L, float* params, const float* grad, float*
     W2b[j] = to_bf16(p);
     W2Tb[(j % kNnHidden) * kNnHidden + j / kNnHidden] = to_bf16(p);
   }
+}
+__global__ void adam_kernel(NnLayout L, float* params, const float* grad, float* m, float* v,
+                            float lr, float b1c, float b2c, unsigned short* W1b,
+                            unsigned short* W2b, unsigned short* W2Tb) {
+  adam_body(L, params, grad, m, v, lr, b1c, b2c, W1b, W2b, W2Tb, blockIdx.x);
 }
 
 __global__ void refresh_bf16_kernel(NnLayout L, const float* params, unsigned short* W1b,
@@ -509,12 +533,14 @@ __global__ __launch_bounds__(64) void apply_guess_kernel(Geometry g, Tables t, c
   }
 }
 
-// Zero the scratch columns [from, M) of every transposed array.
-__global__ void zero_tail_kernel(NnLayout L, NnScratch scr, int from) {
+// Zero the scratch columns [from, M) of every transposed array (workgroup bx
+// of gx, grid-stride).
+__device__ __forceinline__ void zero_tail_body(const NnLayout& L, const NnScratch& scr, int from,
+                                               int bx, int gx) {
   const int width = scr.M - from;
   const long long total = (long long)(L.KP + 3 * kNnHidden) * width;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
+  for (long long e = bx * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gx * blockDim.x) {
     const int row = (int)(e / width);
     const int c = from + (int)(e % width);
     if (row < L.KP) scr.XT[(size_t)row * scr.M + c] = 0;
@@ -522,6 +548,68 @@ __global__ void zero_tail_kernel(NnLayout L, NnScratch scr, int from) {
     else if (row < L.KP + 2 * kNnHidden) scr.dZ1T[(size_t)(row - L.KP - kNnHidden) * scr.M + c] = 0;
     else scr.dZ2T[(size_t)(row - L.KP - 2 * kNnHidden) * scr.M + c] = 0;
   }
+}
+
+__global__ void zero_tail_kernel(NnLayout L, NnScratch scr, int from) {
+  zero_tail_body(L, scr, from, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------- several networks
+// One training iteration of several networks (one per geometry of a batch) in
+// one launch per kernel: blockIdx.y selects the network, steps[it * njobs +
+// job] its minibatch of iteration it, and a network whose schedule has ended
+// (or whose minibatch needs fewer workgroups) skips.  Each network runs the
+// same kernels on the same data in the same order as when trained alone.
+__device__ __forceinline__ const NnTrainStep& train_step(const NnTrainStep* steps, int njobs,
+                                                         int it) {
+  return steps[(size_t)it * njobs + blockIdx.y];
+}
+
+__global__ void zero_tail_many_kernel(const NnTrainJob* jobs, const NnTrainStep* steps, int njobs,
+                                      int it) {
+  const NnTrainStep st = train_step(steps, njobs, it);
+  const NnTrainJob& J = jobs[blockIdx.y];
+  const int from = (st.batch + 63) / 64 * 64;
+  if (!st.active || from >= J.B.scr.M) return;
+  zero_tail_body(J.L, J.B.scr, from, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void mlp_train_many_kernel(const NnTrainJob* jobs,
+                                                             const NnTrainStep* steps, int njobs,
+                                                             int it) {
+  const NnTrainStep st = train_step(steps, njobs, it);
+  if (!st.active || (int)blockIdx.x >= (st.batch + 63) / 64) return;
+  const NnTrainJob& J = jobs[blockIdx.y];
+  const FieldSource src{nullptr, nullptr, nullptr, J.B.hist, J.nsamples, J.perm_a,
+                        st.perm_c, st.batch0, st.batch};
+  mlp_body<true>(J.g, J.L, J.B.params, J.B.W1b, J.B.W2b, J.B.W2Tb, src, nullptr, J.B.scr,
+                 blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void wgrad_many_kernel(const NnTrainJob* jobs,
+                                                        const NnTrainStep* steps, int njobs,
+                                                        int it) {
+  const NnTrainStep st = train_step(steps, njobs, it);
+  const NnTrainJob& J = jobs[blockIdx.y];
+  if (!st.active || (int)blockIdx.x >= wgrad_tiles(J.L)) return;
+  wgrad_body(J.L, J.B.scr, J.B.grad, blockIdx.x);
+}
+
+__global__ void bias_grad_many_kernel(const NnTrainJob* jobs, const NnTrainStep* steps, int njobs,
+                                      int it) {
+  const NnTrainStep st = train_step(steps, njobs, it);
+  if (!st.active) return;
+  const NnTrainJob& J = jobs[blockIdx.y];
+  bias_grad_body(J.L, J.B.scr, (st.batch + 63) / 64, J.B.grad, J.B.loss);
+}
+
+__global__ void adam_many_kernel(const NnTrainJob* jobs, const NnTrainStep* steps, int njobs,
+                                 int it) {
+  const NnTrainStep st = train_step(steps, njobs, it);
+  if (!st.active) return;
+  const NnTrainJob& J = jobs[blockIdx.y];
+  adam_body(J.L, J.B.params, J.B.grad, J.B.adam_m, J.B.adam_v, J.lr, st.b1c, st.b2c, J.B.W1b,
+            J.B.W2b, J.B.W2Tb, blockIdx.x);
 }
 
 // out[P] = T_n[P] + s_D y[P] (the raw guess, for reporting).
@@ -580,6 +668,24 @@ hipError_t nn_train_batch(hipStream_t s, const Geometry& g, const NnLayout& L, c
     hipLaunchKernelGGL(adam_kernel, dim3((L.o_norm + 255) / 256), dim3(256), 0, s, L, B.params,
                        B.grad, B.adam_m, B.adam_v, lr, b1c, b2c, B.W1b, B.W2b, B.W2Tb);
   }
+  return hipGetLastError();
+}
+
+hipError_t nn_train_many(hipStream_t s, const NnTrainJob* jobs, const NnTrainStep* steps,
+                         int njobs, int it, int max_kp) {
+  if (njobs <= 0) return hipSuccess;
+  const dim3 per(1, njobs);
+  const int nwg = (kNnBatch + 63) / 64;
+  const int tiles = 8 * (max_kp / 16) + 64;
+  const int adam_blocks = (kNnHidden * max_kp + kNnHidden * kNnHidden + 4 * kNnHidden + 255) / 256;
+  hipLaunchKernelGGL(zero_tail_many_kernel, dim3(256, njobs), dim3(256), 0, s, jobs, steps, njobs,
+                     it);
+  hipLaunchKernelGGL(mlp_train_many_kernel, dim3(nwg, njobs), dim3(256), 0, s, jobs, steps, njobs,
+                     it);
+  hipLaunchKernelGGL(wgrad_many_kernel, dim3(tiles, njobs), dim3(64), 0, s, jobs, steps, njobs, it);
+  hipLaunchKernelGGL(bias_grad_many_kernel, per, dim3(512), 0, s, jobs, steps, njobs, it);
+  hipLaunchKernelGGL(adam_many_kernel, dim3(adam_blocks, njobs), dim3(256), 0, s, jobs, steps,
+                     njobs, it);
   return hipGetLastError();
 }
 
