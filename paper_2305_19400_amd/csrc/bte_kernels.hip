@@ -1774,7 +1774,11 @@ __global__ __launch_bounds__(256) void batch_temperature_kernel(const BatchCtx* 
   ci = __builtin_amdgcn_readfirstlane(max(ci, 0));
   const BatchCtx& c = ctxs[ci];
   if (blk - c.cell_block0 >= c.cell_blocks || step_done(c.ctl)) return;
-  temperature_body(c.sp64.g, c.sp64.t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
+  // geometry and tables by value: read once, since the kernel's own stores
+  // could otherwise alias the context array and force them to be reloaded
+  const Geometry g = c.sp64.g;
+  const Tables t = c.sp64.t;
+  temperature_body(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
 }
 
 __global__ __launch_bounds__(kReduceBlock) void batch_control_kernel(BatchCtx* ctxs) {
