@@ -50,13 +50,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 struct CompSum {
   double s = 0.0, c = 0.0;
   __device__ __forceinline__ void add(double v) {
-#ifdef BTE_PLAIN_SUMS
-    s += v;
-#else
     const double t = s + v;
     c += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
     s = t;
-#endif
   }
   __device__ __forceinline__ double value() const { return s + c; }
 };
