@@ -139,6 +139,8 @@ Layout make_layout(const Shape& s) {
   return L;
 }
 
+constexpr long long kMaxCells = (INT_MAX - 255) / 8;  // slab bytes fit a signed 32-bit offset
+
 int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte_options* o,
              Shape* out) {
   if (!m || !d || !b || !o) return fail(BTE_E_INVAL, "null argument");
@@ -149,7 +151,10 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   for (int a = 0; a < m->dim; ++a)
     if (!(m->h[a] > 0.0) || !std::isfinite(m->h[a])) return fail(BTE_E_INVAL, "h[%d] must be positive", a);
   const long long nc = (long long)m->n[0] * m->n[1] * m->n[2];
-  if (nc > INT_MAX / 2) return fail(BTE_E_INVAL, "too many cells (%lld)", nc);
+  // the sweeps address one (band, direction) slab of FP64 values with 32-bit
+  // byte offsets
+  if (nc > kMaxCells)
+    return fail(BTE_E_INVAL, "too many cells (%lld; at most %lld)", nc, (long long)kMaxCells);
   if (d->n < 1 || !d->s || !d->w) return fail(BTE_E_INVAL, "need at least one direction");
   if (d->n > 65535) return fail(BTE_E_INVAL, "at most 65535 directions");
   if (b->n < 1 || !b->omega || !b->domega) return fail(BTE_E_INVAL, "need at least one band");

@@ -91,6 +91,10 @@ def test_validation_rejects_bad_inputs_without_device():
     # 2D mesh with nz != 1
     flat = base.copy(n=[16, 16, 2])
     assert _create_status(flat)[0] == bte.BTE_E_INVAL
+    # more cells than 32-bit slab offsets reach (rejected before any array is read)
+    huge = base.copy(dim=3, n=[700, 700, 700], h=[1e-8, 1e-8, 1e-8])
+    rc, msg = _create_status(huge)
+    assert rc == bte.BTE_E_INVAL and "too many cells" in msg
 
 
 def test_workspace_checks_without_device():
