@@ -159,6 +159,15 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   if (d->n > 65535) return fail(BTE_E_INVAL, "at most 65535 directions");
   if (b->n < 1 || !b->omega || !b->domega) return fail(BTE_E_INVAL, "need at least one band");
   if (b->n > 65535) return fail(BTE_E_INVAL, "at most 65535 band entries");
+  {
+    // a side's wall table [band entry][face] is addressed with 32-bit byte offsets too
+    const long long nx = m->n[0], ny = m->n[1], nz = m->n[2];
+    const long long faces =
+        m->dim == 3 ? std::max(ny * nz, std::max(nx * nz, nx * ny)) : std::max(nx, ny);
+    if ((long long)b->n * faces > kMaxCells)
+      return fail(BTE_E_INVAL, "band entries x wall faces too large (%lld x %lld)",
+                  (long long)b->n, faces);
+  }
   if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(BTE_E_INVAL, "dt must be positive");
   if (o->scheme != BTE_IMPLICIT_JACOBI && o->scheme != BTE_EXPLICIT_EULER)
     return fail(BTE_E_INVAL, "unknown scheme %d", o->scheme);

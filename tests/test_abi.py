@@ -95,6 +95,10 @@ def test_validation_rejects_bad_inputs_without_device():
     huge = base.copy(dim=3, n=[700, 700, 700], h=[1e-8, 1e-8, 1e-8])
     rc, msg = _create_status(huge)
     assert rc == bte.BTE_E_INVAL and "too many cells" in msg
+    # wall tables past 32-bit offsets: 4 band entries x 10^8 faces of a z side
+    wide = base.copy(dim=3, n=[10000, 10000, 2], h=[1e-8, 1e-8, 1e-8])
+    rc, msg = _create_status(wide)
+    assert rc == bte.BTE_E_INVAL and "wall faces" in msg
 
 
 def test_workspace_checks_without_device():
