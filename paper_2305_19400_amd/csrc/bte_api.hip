@@ -1313,7 +1313,9 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   for (int l = 0; l < kBatchLists; ++l)
     b->sweep_blocks[l] = cus * batch_sweep_occupancy(b->precision, l);
   int blocks = 0;
-  for (int i = 0; i < n; ++i) blocks += (ctxs[i]->s.nc + 31) / 32;
+  for (int i = 0; i < n; ++i)
+    blocks += (ctxs[i]->s.nc + temp_cells_per_block(ctxs[i]->s.nb) - 1) /
+              temp_cells_per_block(ctxs[i]->s.nb);
   b->temp_blocks = blocks;
 #define BATCH_TRY(expr)                                                               \
   do {                                                                                \
@@ -1466,7 +1468,8 @@ int bte_batch_step(bte_batch* b, int nsteps, bte_step_stats* stats) {
       d.max_inner = ctx->opt.max_inner;
       d.fixed_k = 0;
       d.cell_block0 = (i == 0) ? 0 : b->h_ctx[i - 1].cell_block0 + b->h_ctx[i - 1].cell_blocks;
-      d.cell_blocks = (ctx->s.nc + 31) / 32;
+      d.cell_blocks =
+          (ctx->s.nc + temp_cells_per_block(ctx->s.nb) - 1) / temp_cells_per_block(ctx->s.nb);
     }
     ctx = nullptr;
     HIP_TRY(hipMemcpyAsync(b->d_ctx, b->h_ctx, sizeof(BatchCtx) * n, hipMemcpyHostToDevice,

@@ -1321,36 +1321,33 @@ template hipError_t launch_sweep<float>(hipStream_t, const Geometry&, const Tabl
                                         const double*);
 
 // ---------------------------------------------------------------- temperature
-// Each cell is handled by kLanesPerCell lanes of one wavefront; lane l of a
+// Each cell is handled by LANES lanes of one wavefront (temp_lanes); lane l of a
 // cell owns the bands b = l, l + L, l + 2L, ...  Sums over bands are completed
 // with an xor butterfly inside the lane group and the group's first lane's
 // total is then broadcast, so every lane of the group holds bit-identical
 // values (whatever the compiler fuses into the butterfly) and the group's
 // Newton iterations stay in lockstep.
-#ifndef BTE_T_LANES
-#define BTE_T_LANES 8
-#endif
-constexpr int kLanesPerCell = BTE_T_LANES;
-
+template <int LANES>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma clang fp contract(off)
 #pragma unroll
-  for (int m = 1; m < kLanesPerCell; m <<= 1) v += __shfl_xor(v, m, 64);
-  if (kLanesPerCell > 1) {
+  for (int m = 1; m < LANES; m <<= 1) v += __shfl_xor(v, m, 64);
+  if (LANES > 1) {
     const int lane = threadIdx.x & 63;
-    v = __shfl(v, lane & ~(kLanesPerCell - 1), 64);
+    v = __shfl(v, lane & ~(LANES - 1), 64);
   }
   return v;
 }
 
 // Partial F(T) = W sum_b f_b I0_b(T) and dF/dT over this lane's bands; f_b is
 // 1/tau_b (relaxation-time weighted) or 1 (plain energy).
+template <int LANES>
 __device__ __forceinline__ void relation_part(const Tables& t, int nb, int l, double T, double& F,
                                               double& dF) {
 #pragma clang fp contract(off)
   double f = 0.0, df = 0.0;
 #pragma unroll 4
-  for (int b = l; b < nb; b += kLanesPerCell) {
+  for (int b = l; b < nb; b += LANES) {
     const double x = t.xfac[b] / T;
     const double em1 = expm1(x);
     const double i0 = t.Cb[b] / em1;
@@ -1365,14 +1362,15 @@ __device__ __forceinline__ void relation_part(const Tables& t, int nb, int l, do
 // partials, invert the temperature relation by Newton from the current T
 // (accept-first, quadratic convergence; Sec. 2.2 and Sec. 3.2 temperature
 // update), then refresh the equilibrium intensities I0[b][P] for the next sweep.
+template <int LANES>
 __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables& t,
                                                  const double* __restrict__ S,
                                                  double* __restrict__ T, double* __restrict__ I0,
                                                  double* __restrict__ E, Control* ctl,
                                                  const int bx) {
 #pragma clang fp contract(on)  // fuse a*b+c only within one expression
-  const int l = threadIdx.x % kLanesPerCell;
-  const int P = bx * (256 / kLanesPerCell) + threadIdx.x / kLanesPerCell;
+  const int l = threadIdx.x % LANES;
+  const int P = bx * (256 / LANES) + threadIdx.x / LANES;
   const bool active = P < g.nc;
   const int Pc = active ? P : 0;
   const size_t ncp = (size_t)g.ncp;
@@ -1384,13 +1382,13 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
     // G and E in order.
     constexpr int kChunk = 4;
     const size_t qstride = (size_t)g.nb * ncp;
-    for (int b0 = l; b0 < g.nb; b0 += kLanesPerCell * kChunk) {
+    for (int b0 = l; b0 < g.nb; b0 += LANES * kChunk) {
       CompSum s[kChunk];
       for (int q = 0; q < g.ndg; ++q) {
         double v[kChunk];
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
-          const int b = b0 + i * kLanesPerCell;
+          const int b = b0 + i * LANES;
           v[i] = b < g.nb ? S[(size_t)q * qstride + (size_t)b * ncp + Pc] : 0.0;
         }
 #pragma unroll
@@ -1398,7 +1396,7 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
       }
 #pragma unroll
       for (int i = 0; i < kChunk; ++i) {
-        const int b = b0 + i * kLanesPerCell;
+        const int b = b0 + i * LANES;
         if (b < g.nb) {
           Gs.add(t.fweight[b] * s[i].value());
           Es.add(s[i].value());
@@ -1407,15 +1405,15 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
     }
   }
   const double Gp = Gs.value(), Ep = Es.value();
-  const double G = group_sum(Gp);
-  const double En = group_sum(Ep);
+  const double G = group_sum<LANES>(Gp);
+  const double En = group_sum<LANES>(Ep);
   double Tc = T[Pc];
   int it = 0;
   bool ok = (G > 0.0) && isfinite(G) && (Tc > 0.0);
   if (ok) {
     double Fp, dFp;
-    relation_part(t, g.nb, l, Tc, Fp, dFp);
-    double F = group_sum(Fp), dF = group_sum(dFp);
+    relation_part<LANES>(t, g.nb, l, Tc, Fp, dFp);
+    double F = group_sum<LANES>(Fp), dF = group_sum<LANES>(dFp);
     if (fabs(F - G) > kNewtonAcceptRel * G) {
       ok = false;
       for (it = 1; it <= kNewtonMaxIters; ++it) {
@@ -1426,9 +1424,9 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
           ok = true;
           break;
         }
-        relation_part(t, g.nb, l, Tc, Fp, dFp);
-        F = group_sum(Fp);
-        dF = group_sum(dFp);
+        relation_part<LANES>(t, g.nb, l, Tc, Fp, dFp);
+        F = group_sum<LANES>(Fp);
+        dF = group_sum<LANES>(dFp);
       }
     }
   }
@@ -1438,7 +1436,7 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
     return;
   }
 #pragma unroll 4
-  for (int b = l; b < g.nb; b += kLanesPerCell)
+  for (int b = l; b < g.nb; b += LANES)
     I0[(size_t)b * ncp + P] = equilibrium(t.Cb[b], t.xfac[b], Tc);
   if (l == 0) {
     T[P] = Tc;
@@ -1447,20 +1445,24 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
   }
 }
 
+template <int LANES>
 __global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
                                                           const double* __restrict__ S,
                                                           double* __restrict__ T,
                                                           double* __restrict__ I0,
                                                           double* __restrict__ E, Control* ctl) {
   if (step_done(ctl)) return;
-  temperature_body(g, t, S, T, I0, E, ctl, blockIdx.x);
+  temperature_body<LANES>(g, t, S, T, I0, E, ctl, blockIdx.x);
 }
 
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* S, double* T, double* I0, double* E, Control* ctl) {
-  const int cells_per_block = 256 / kLanesPerCell;
+  const int cells_per_block = temp_cells_per_block(g.nb);
   const dim3 grid((g.nc + cells_per_block - 1) / cells_per_block);
-  hipLaunchKernelGGL(temperature_kernel, grid, dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
+  if (temp_lanes(g.nb) == 4)
+    hipLaunchKernelGGL(temperature_kernel<4>, grid, dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
+  else
+    hipLaunchKernelGGL(temperature_kernel<8>, grid, dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
   return hipGetLastError();
 }
 
@@ -1774,7 +1776,10 @@ __global__ __launch_bounds__(256) void batch_temperature_kernel(const BatchCtx* 
   // could otherwise alias the context array and force them to be reloaded
   const Geometry g = c.sp64.g;
   const Tables t = c.sp64.t;
-  temperature_body(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
+  if (temp_lanes(g.nb) == 4)
+    temperature_body<4>(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
+  else
+    temperature_body<8>(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
 }
 
 __global__ __launch_bounds__(kReduceBlock) void batch_control_kernel(BatchCtx* ctxs) {
