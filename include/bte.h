@@ -237,8 +237,9 @@ int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const
  * 2 planes of the flattened (x, y) plane (reported as 0 rows), x 1-4
  * direction groups.  *ry and *rz are in/out: a positive value on entry
  * restricts the search to that row / plane count, and *ry = -1 to the layouts
- * a batch accepts (4 rows in 2D; 2x2, 1x4 or the flattened plane in 3D).  The choice is returned in *ry, *rz, *ndg and its sweep time
- * (measured now or recorded in the cache) in *sweep_ms (all nullable; -1 for
+ * a batch accepts (4 rows in 2D; 2x2, 1x4 or the flattened plane in 3D).
+ * The choice is returned in *ry, *rz, *ndg and its sweep time (measured now
+ * or recorded in the cache) in *sweep_ms (all nullable; -1 for
  * shapes with a single layout).  BTE_E_INVAL if the restriction matches no
  * layout. */
 int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry, int* rz, int* ndg,
@@ -246,14 +247,17 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry, int* rz, int* nd
 
 /* Batched stepping of independent contexts (geometries of any size, 2D or
  * 3D, one precision, sharing one stream): every inner iteration of all of them
- * runs as one persistent sweep over a work list of (geometry, tile, band,
- * direction group) items -- largest geometry first, converged geometries
- * skipped -- followed by batched temperature and convergence kernels.  With
- * use_graph (and a non-null stream) that iteration is captured once as a HIP
- * graph and replayed until every geometry has converged.  Each context gives
- * exactly the results it gives when stepped alone.  Batches need the 4-row
- * sweep layout, the implicit scheme, and warm start NONE or T.  The batch
- * holds small device arrays of its own (descriptors, work list). */
+ * runs as persistent sweeps over work lists of (geometry, tile, band,
+ * direction group) items -- one list per kernel family, largest geometry
+ * first, converged geometries skipped -- followed by batched temperature and
+ * convergence kernels.  With use_graph (and a non-null stream) that iteration
+ * is captured once as a HIP graph and replayed until every geometry has
+ * converged.  Networks of the learned warm start that fall due in the same
+ * step train together.  Each context gives exactly the results it gives when
+ * stepped alone.  Batches need a layout bte_autotune's *ry = -1 search
+ * allows (4 rows in 2D; 2x2, 1x4 or the flattened plane in 3D), the implicit
+ * scheme, and warm start NONE or T.  The batch holds small device arrays of
+ * its own (descriptors, work lists, training schedules). */
 typedef struct bte_batch bte_batch;
 int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out);
 /* stats (nullable): [nsteps][n] */
