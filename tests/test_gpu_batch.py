@@ -141,25 +141,34 @@ def test_batch_mixes_3d_layouts(gpu, monkeypatch, precision, layout3d):
     assert ok
 
 
-def test_batch_with_learned_warm_start(gpu):
+@pytest.mark.parametrize("train_steps", [(3, 3, 3), (3, 4, 3)])
+def test_batch_with_learned_warm_start(gpu, train_steps):
+    """The networks of a batch train together when their training falls due
+    in the same step (and in separate groups when it does not); each geometry
+    still matches its solo run bit for bit, losses included."""
     import torch
     insts = geometries(I.PRECISION_FP32_MIXED)[:3]
     stream = torch.cuda.Stream()
-    opts = dict(precision=gpu.BTE_FP32_MIXED, warm_start=gpu.BTE_WARM_T, nn_train_steps=3,
-                nn_seed=2)
-    announce("batch with warm start (train after 3 steps)")
+
+    def opts(i):
+        return dict(precision=gpu.BTE_FP32_MIXED, warm_start=gpu.BTE_WARM_T,
+                    nn_train_steps=train_steps[i], nn_seed=2)
+    announce(f"batch with warm start (train after {train_steps} steps)")
     ref = []
-    for inst in insts:
-        with gpu.Solver(inst, stream=stream, **opts) as s:
-            st = s.step(6)
-            ref.append(([x["inner"] for x in st], s.temperature()))
+    for i, inst in enumerate(insts):
+        with gpu.Solver(inst, stream=stream, **opts(i)) as s:
+            st = s.step(7)
+            ref.append(([x["inner"] for x in st], s.temperature(),
+                        [x["nn_loss"] for x in st]))
     announce("solo runs done; batch of the same")
-    sols = [gpu.Solver(inst, stream=stream, **opts) for inst in insts]
+    sols = [gpu.Solver(inst, stream=stream, **opts(i)) for i, inst in enumerate(insts)]
     with gpu.Batch(sols) as batch:
-        st = batch.step(6)
+        st = batch.step(7)
     for i, s in enumerate(sols):
-        assert [st[k][i]["inner"] for k in range(6)] == ref[i][0]
-        assert st[2][i]["trained"] == 1 and all(st[k][i]["warm"] for k in range(3, 6))
+        n = train_steps[i]
+        assert [st[k][i]["inner"] for k in range(7)] == ref[i][0]
+        assert st[n - 1][i]["trained"] == 1 and all(st[k][i]["warm"] for k in range(n, 7))
+        assert [st[k][i]["nn_loss"] for k in range(7)] == ref[i][2]
         assert same(f"warm geometry {i} T", s.temperature(), ref[i][1], insts[i])
         s.close()
 
