@@ -1189,8 +1189,17 @@ template <typename Real, int RZ, bool SHIFT>
 __global__ __launch_bounds__(kSweepBlock) void sweep3d_flat_kernel(const SweepParams<Real> p,
                                                                    const int nft, const int dgs) {
   if (step_done(p.ctl)) return;
-  flat3d_body<Real, RZ, SHIFT>(p, nft, dgs, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
-                               gridDim.y);
+  // Workgroups go to the eight XCDs in turn, and each XCD has its own L2.  A
+  // plane tile reads the row before its first and after its last cell from
+  // the neighbouring tiles, so when the tile count divides by eight, each XCD
+  // is given a contiguous range of tiles (neighbours then share an L2).  The
+  // partials stay indexed by tile, so results do not change.
+  int bx = blockIdx.x;
+  if ((gridDim.x & 7) == 0) {
+    const int per_xcd = gridDim.x >> 3;
+    bx = (bx & 7) * per_xcd + (bx >> 3);
+  }
+  flat3d_body<Real, RZ, SHIFT>(p, nft, dgs, bx, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
 SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int rz,

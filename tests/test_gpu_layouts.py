@@ -62,6 +62,9 @@ def case_2d_narrow():
 
 
 def case_3d():
+    # flattened plane: 4 plane tiles x 2 (4 planes) or 4 (2 planes) z blocks, a
+    # tile count divisible by 8, so its launch takes the XCD-ordered tile mapping
+    # (the narrow case below does not)
     inst = I.gaussian_3d(70, 11, 7, 2, 8, 3, seed=53, precision=I.PRECISION_FP64, nsteps=2)
     inst.h = [1e-8, 1.2e-8, 0.9e-8]
     inst.name = "layouts3d_70x11x7"
