@@ -1,0 +1,51 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
+bytes per sweep launch, and the rule that measured traffic is reported only
+for the kernel source it was measured on."""
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2305_19400_amd import inputs as I  # noqa: E402
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_exits_with_a_message(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_sweep_bytes_of_the_2d_workload():
+    # 128 x 128 cells x 400 directions x 55 band entries: I^k and I^n read and
+    # I^{k+1} written per update (8 B each in FP64, 4 B in FP32), plus the
+    # per-(band, cell) equilibrium read and energy partial write (8 B each)
+    inst = I.config_c2()
+    n_dof = 128 * 128 * 400 * 55
+    assert inst.n_dof == n_dof
+    assert bench.sweep_bytes(inst, 8) == n_dof * 24 + 55 * 128 * 128 * 16
+    assert bench.sweep_bytes(inst, 4) == n_dof * 12 + 55 * 128 * 128 * 16
+
+
+def test_traffic_only_for_the_measured_source(tmp_path):
+    src = tmp_path / "kernels.hip"
+    src.write_bytes(b"__global__ void k() {}\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    counters = tmp_path / "counters.json"
+    counters.write_text(json.dumps({"kernel_source_sha256": sha,
+                                    "traffic_bytes_per_launch": 1.25e9}))
+    assert bench.measured_traffic(str(src), str(counters)) == 1.25e9
+    src.write_bytes(b"__global__ void k() { }\n")  # source changed since the counters
+    assert bench.measured_traffic(str(src), str(counters)) is None
+    assert bench.measured_traffic(str(src), str(tmp_path / "missing.json")) is None
+    counters.write_text("not json")
+    assert bench.measured_traffic(str(src), str(counters)) is None
