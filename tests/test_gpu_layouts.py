@@ -113,6 +113,31 @@ def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     assert errT <= 1e-10 and errI <= 1e-10
 
 
+@pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 16, 0, 2), ("3d", 2, 2, 1), ("3d", 1, 4, 2),
+                                             ("3d", 2, 4, 3), ("3d", 0, 4, 1), ("3d", 0, 2, 2),
+                                             ("3dn", 1, 4, 1)])
+def test_explicit_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
+    """Forward-Euler steps (one sweep each, the update scaled by dt instead of
+    the implicit diagonal) through every sweep family and layout."""
+    from oracle import Oracle
+    inst = CASES[dim]()
+    dt = 2e-13  # inside the forward-Euler stability limit of these meshes
+    set_layout(monkeypatch, ry, rz, ndg)
+    ref = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=dt)
+    ref_st = ref.run(4)
+    announce(f"{inst.name} explicit ry={ry} rz={rz} ndg={ndg}")
+    with gpu.Solver(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=dt) as sol:
+        st = sol.step(4)
+        T, Iq = sol.temperature(), sol.intensity()
+    assert all(s["inner"] == 1 for s in st) and all(s["inner"] == 1 for s in ref_st)
+    I_ref = np.ascontiguousarray(ref.intensity().transpose(2, 1, 0))
+    errT = float(np.max(np.abs(T - ref.temperature()) / ref.temperature()))
+    errI = float(np.max(np.abs(Iq - I_ref) / np.abs(I_ref)))
+    print(f"explicit T {errT:.2e} I {errI:.2e}", flush=True)
+    assert errT <= 1e-10 and errI <= 1e-10
+    assert float(np.max(np.abs(T - inst.T_init))) > 1e-3  # the steps changed the field
+
+
 @pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("2dn", 4, 0, 1), ("3d", 1, 4, 2),
                                              ("3d", 0, 4, 1), ("3dn", 0, 2, 2)])
 def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
