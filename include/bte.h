@@ -65,9 +65,12 @@ enum bte_wall { BTE_WALL_ISOTHERMAL = 0, BTE_WALL_SPECULAR = 1, BTE_WALL_SYMMETR
  * updated once after the step (Sec. 3.2, postStepFunction). */
 enum bte_scheme { BTE_IMPLICIT_JACOBI = 0, BTE_EXPLICIT_EULER = 1 };
 
-/* Storage / arithmetic of the intensity sweep.  FP32_MIXED keeps intensities
- * and sweep arithmetic in FP32 and the energy reduction, temperature inversion
- * and residual norms in FP64. */
+/* Storage / arithmetic of the intensity sweep.  FP32_MIXED stores each
+ * intensity as its FP32 deviation from I0_b at the coldest input temperature; the
+ * sweep computes the update in FP64 and rounds it once to storage, and the
+ * energy reduction, temperature inversion and residual norms are FP64.
+ * FP32_MIXED is for the implicit scheme: bte_create rejects it with
+ * EXPLICIT_EULER (BTE_E_INVAL). */
 enum bte_precision { BTE_FP64 = 0, BTE_FP32_MIXED = 1 };
 
 /* Temperature definition.  TAU_WEIGHTED: W sum_b I0_b(T)/tau_b =

@@ -178,6 +178,8 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   if (!m->T_init) return fail(BTE_E_INVAL, "T_init is required");
   if (o->warm_start < BTE_WARM_NONE || o->warm_start > BTE_WARM_T_SHIFT)
     return fail(BTE_E_INVAL, "unknown warm_start %d", o->warm_start);
+  if (o->precision != BTE_FP64 && o->scheme == BTE_EXPLICIT_EULER)
+    return fail(BTE_E_INVAL, "the explicit scheme needs FP64 storage");
   if (o->warm_start != BTE_WARM_NONE && o->scheme != BTE_IMPLICIT_JACOBI)
     return fail(BTE_E_INVAL, "the learned warm start seeds the implicit inner iteration only");
   Shape s{};
