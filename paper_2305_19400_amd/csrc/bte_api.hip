@@ -178,8 +178,6 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   if (!m->T_init) return fail(BTE_E_INVAL, "T_init is required");
   if (o->warm_start < BTE_WARM_NONE || o->warm_start > BTE_WARM_T_SHIFT)
     return fail(BTE_E_INVAL, "unknown warm_start %d", o->warm_start);
-  if (o->precision != BTE_FP64 && o->scheme == BTE_EXPLICIT_EULER)
-    return fail(BTE_E_INVAL, "the explicit scheme needs FP64 storage");
   if (o->warm_start != BTE_WARM_NONE && o->scheme != BTE_IMPLICIT_JACOBI)
     return fail(BTE_E_INVAL, "the learned warm start seeds the implicit inner iteration only");
   Shape s{};
@@ -200,6 +198,12 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   // allow fewer waves); otherwise 2 rows x 2 planes per wave with FP64
   // storage and 1 row x 4 planes with FP32 storage (the faster at 64^3).
   const bool fp32 = o->precision != BTE_FP64;
+  // The tiled kernels evaluate the FP32-storage update in the direct form
+  // (I^n/dt + I0/tau + sum c I_up) * scale, which is the implicit Jacobi
+  // update only; forward Euler also needs -(1/tau + sum c) I^n.  The
+  // cell-per-thread kernel forms the increment of I^k for either scheme, so
+  // FP32 storage with the explicit scheme always takes it (no overrides).
+  const bool cell_only = fp32 && o->scheme == BTE_EXPLICIT_EULER;
   int ry_dflt = 0, rz_dflt = 0, kind_dflt = -1;
   if (s.dim == 3) {
     const double lanes_used = (double)s.nx / (64.0 * ((s.nx + 63) / 64));
@@ -213,7 +217,8 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   }
   s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", ry_dflt),
                            env_int("BTE_SWEEP_RZ", rz_dflt), env_int("BTE_SWEEP_NDG", 0),
-                           env_int("BTE_SWEEP_KIND", kind_dflt));
+                           cell_only ? (int)kSweepCellPerThread
+                                     : env_int("BTE_SWEEP_KIND", kind_dflt));
   s.ndg_cap = s.plan.ndg;
   s.nparts_cap = s.plan.nparts;
   if (s.plan.kind == kSweepColumnWalk2D) {

@@ -79,9 +79,6 @@ def test_validation_rejects_bad_inputs_without_device():
     assert _create_status(base, dt=-1.0)[0] == bte.BTE_E_INVAL
     assert _create_status(base, scheme=7)[0] == bte.BTE_E_INVAL
     assert _create_status(base, precision=3)[0] == bte.BTE_E_INVAL
-    # FP32 storage is for the implicit scheme only
-    rc, msg = _create_status(base, precision=bte.BTE_FP32_MIXED, scheme=bte.BTE_EXPLICIT_EULER)
-    assert rc == bte.BTE_E_INVAL and "explicit" in msg
     # non-positive initial temperature
     cold = base.copy()
     cold.T_init[5] = -1.0

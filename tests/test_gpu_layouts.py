@@ -138,6 +138,36 @@ def test_explicit_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     assert float(np.max(np.abs(T - inst.T_init))) > 1e-3  # the steps changed the field
 
 
+@pytest.mark.parametrize("dim,layout", [("2d", None), ("3d", None), ("3dn", None),
+                                        ("2d", (8, 0, 3)), ("3d", (1, 4, 2)), ("3d", (0, 4, 1))])
+def test_fp32_explicit_matches_oracle(gpu, monkeypatch, dim, layout):
+    """FP32 storage with forward-Euler steps sweeps one cell per thread
+    whatever layout is requested (the tiled kernels' FP32 update is the
+    implicit one), and matches the FP64 oracle to the FP32 bar."""
+    from oracle import Oracle
+    inst = CASES[dim]()
+    dt = 2e-13
+    if layout is not None:
+        set_layout(monkeypatch, *layout)
+    ref = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=dt)
+    ref.run(4)
+    announce(f"{inst.name} fp32 explicit, requested layout {layout}")
+    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED, scheme=I.SCHEME_EXPLICIT_EULER,
+                    dt=dt) as sol:
+        assert sol.sweep_layout()["kind"] == 0
+        assert sol.autotune()[:3] == (1, 1, 1)  # nothing to tune: the layout stays
+        assert sol.sweep_layout()["kind"] == 0
+        st = sol.step(4)
+        T, Iq = sol.temperature(), sol.intensity()
+    assert all(s["inner"] == 1 for s in st)
+    I_ref = np.ascontiguousarray(ref.intensity().transpose(2, 1, 0))
+    errT = float(np.max(np.abs(T - ref.temperature()) / ref.temperature()))
+    errI = float(np.max(np.abs(Iq - I_ref) / np.abs(I_ref)))
+    print(f"fp32 explicit T {errT:.2e} I {errI:.2e}", flush=True)
+    assert errT <= 1e-5 and errI <= 1e-5
+    assert float(np.max(np.abs(T - inst.T_init))) > 1e-3
+
+
 @pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("2dn", 4, 0, 1), ("3d", 1, 4, 2),
                                              ("3d", 0, 4, 1), ("3dn", 0, 2, 2)])
 def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
