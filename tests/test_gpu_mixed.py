@@ -43,14 +43,17 @@ def small_2d():
     return I.strip_2d(32, 32, 20, 20, 40, seed=2, nsteps=5)
 
 
-@pytest.mark.parametrize("maker", [small_2d, small_3d])
-def test_fp32_temperature_vs_oracle(gpu, maker):
+@pytest.mark.parametrize("maker,tdef", [(small_2d, I.TDEF_TAU_WEIGHTED),
+                                        (small_3d, I.TDEF_TAU_WEIGHTED),
+                                        (small_3d, I.TDEF_ENERGY)])
+def test_fp32_temperature_vs_oracle(gpu, maker, tdef):
     from oracle import Oracle
     inst = maker()
-    ref = Oracle(inst)
+    ref = Oracle(inst, t_definition=tdef)
     ref_st = ref.run(inst.nsteps)
-    announce(f"fp32 {inst.name} vs oracle, {inst.nsteps} steps, oracle k={[s['inner'] for s in ref_st]}")
-    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED) as sol:
+    announce(f"fp32 {inst.name} tdef={tdef} vs oracle, {inst.nsteps} steps, "
+             f"oracle k={[s['inner'] for s in ref_st]}")
+    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED, t_definition=tdef) as sol:
         st = sol.step(inst.nsteps)
         T = sol.temperature()
         Iq = sol.intensity()
