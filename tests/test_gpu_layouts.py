@@ -138,6 +138,47 @@ def test_explicit_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     assert float(np.max(np.abs(T - inst.T_init))) > 1e-3  # the steps changed the field
 
 
+DEGENERATE = [(2, (1, 9), None), (2, (1, 9), (16, 0, 2)), (2, (11, 1), None), (2, (11, 1), "cell"),
+              (2, (1, 1), None), (3, (1, 6, 5), None), (3, (1, 6, 5), (2, 2, 1)),
+              (3, (7, 1, 4), (1, 4, 2)), (3, (7, 1, 4), (0, 4, 1)), (3, (6, 5, 1), (2, 4, 3)),
+              (3, (6, 5, 1), None), (3, (1, 1, 1), None), (3, (1, 1, 1), (2, 2, 1)),
+              (3, (1, 1, 7), (0, 4, 1)), (3, (1, 1, 7), (1, 4, 1))]
+
+
+@pytest.mark.parametrize("dim,n,layout", DEGENERATE)
+def test_degenerate_mesh_matches_oracle(gpu, monkeypatch, dim, n, layout):
+    """Axes one cell wide (every cell between two walls of that axis) and
+    single-cell meshes, in 2D and 3D, through the default and requested
+    layouts, with the mixed wall kinds."""
+    from oracle import Oracle
+    seed = 70 + sum(n)
+    if dim == 2:
+        inst = I.strip_2d(n[0], n[1], 2, 8, 4, seed=seed, strip_cells=1, nsteps=2)
+    else:
+        inst = I.gaussian_3d(n[0], n[1], n[2], 2, 8, 3, seed=seed, sigma_cells=1.0,
+                             precision=I.PRECISION_FP64, nsteps=2)
+    inst.name = f"degenerate{dim}d_" + "x".join(str(v) for v in n)
+    inst = mixed_walls(inst, seed + 10)
+    if layout == "cell":
+        monkeypatch.setenv("BTE_SWEEP_KIND", "0")
+    elif layout is not None:
+        set_layout(monkeypatch, *layout)
+    ref = Oracle(inst)
+    sched = [s["inner"] for s in ref.run(inst.nsteps)]
+    announce(f"{inst.name} layout={layout} sched={sched}")
+    with gpu.Solver(inst) as sol:
+        if layout == "cell":
+            assert sol.sweep_layout()["kind"] == 0
+        sol.step(inst.nsteps, fixed_inner=sched)
+        T, Iq = sol.temperature(), sol.intensity()
+    I_ref = np.ascontiguousarray(ref.intensity().transpose(2, 1, 0))
+    errT = float(np.max(np.abs(T - ref.temperature()) / ref.temperature()))
+    errI = float(np.max(np.abs(Iq - I_ref) / np.abs(I_ref)))
+    print(f"T {errT:.2e} I {errI:.2e}", flush=True)
+    assert errT <= 1e-10 and errI <= 1e-10
+    assert float(np.max(np.abs(T - inst.T_init))) > 1e-3
+
+
 @pytest.mark.parametrize("dim,layout", [("2d", None), ("3d", None), ("3dn", None),
                                         ("2d", (8, 0, 3)), ("3d", (1, 4, 2)), ("3d", (0, 4, 1))])
 def test_fp32_explicit_matches_oracle(gpu, monkeypatch, dim, layout):
