@@ -141,6 +141,53 @@ def test_batch_mixes_3d_layouts(gpu, monkeypatch, precision, layout3d):
     assert ok
 
 
+def degenerate_geometries(precision):
+    """One-cell-wide axes and single cells, 2D and 3D, with a wall mix per
+    face, beside one ordinary mesh of each dimension."""
+    rng = np.random.default_rng(90)
+    g = [I.strip_2d(1, 9, 2, 8, 4, seed=91, strip_cells=1, nsteps=3),
+         I.strip_2d(11, 1, 2, 8, 4, seed=92, strip_cells=1, nsteps=3),
+         I.strip_2d(1, 1, 2, 8, 4, seed=93, strip_cells=1, nsteps=3),
+         I.strip_2d(20, 33, 3, 8, 4, seed=94, nsteps=3)]
+    g += [I.gaussian_3d(*n, 2, 8, 3, seed=95 + i, sigma_cells=1.0, precision=precision, nsteps=3)
+          for i, n in enumerate([(1, 6, 5), (7, 1, 4), (6, 5, 1), (1, 1, 1), (1, 1, 7), (10, 9, 8)])]
+    kinds = [I.WALL_ISOTHERMAL, I.WALL_SPECULAR, I.WALL_SYMMETRY, I.WALL_ISOTHERMAL,
+             I.WALL_SPECULAR, I.WALL_ISOTHERMAL]
+    for inst in g:
+        inst.precision = precision
+        inst.wall = kinds[:2 * inst.dim] + [I.WALL_ISOTHERMAL] * (6 - 2 * inst.dim)
+        inst.wall_T = [rng.uniform(296.0, 330.0, inst.wall_face_count(f))
+                       if f < 2 * inst.dim and inst.wall[f] == I.WALL_ISOTHERMAL else None
+                       for f in range(6)]
+        inst.T_init = rng.uniform(295.0, 325.0, inst.n_cells)
+    return g
+
+
+@pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
+def test_batch_of_degenerate_meshes(gpu, precision):
+    import torch
+    insts = degenerate_geometries(precision)
+    stream = torch.cuda.Stream()
+    nsteps = 3
+    announce(f"batch of {len(insts)} degenerate geometries, precision={precision}")
+    solos = []
+    for inst in insts:
+        with gpu.Solver(inst, stream=stream) as s:
+            st = s.step(nsteps)
+            solos.append(([x["inner"] for x in st], s.temperature(), s.intensity()))
+    announce("solo runs done; creating the batch")
+    sols = [gpu.Solver(inst, stream=stream) for inst in insts]
+    with gpu.Batch(sols, use_graph=True) as batch:
+        st = batch.step(nsteps)
+    ok = True
+    for i, s in enumerate(sols):
+        assert [st[k][i]["inner"] for k in range(nsteps)] == solos[i][0]
+        ok &= same(f"geometry {i} T", s.temperature(), solos[i][1], insts[i])
+        ok &= same(f"geometry {i} I", s.intensity(), solos[i][2], insts[i])
+        s.close()
+    assert ok
+
+
 @pytest.mark.parametrize("train_steps", [(3, 3, 3), (3, 4, 3)])
 def test_batch_with_learned_warm_start(gpu, train_steps):
     """The networks of a batch train together when their training falls due
