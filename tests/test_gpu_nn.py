@@ -61,10 +61,19 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_forward_backward_vs_reference(gpu, dim):
+@pytest.mark.parametrize("dim,n", [(2, None), (3, None), (2, (1, 9)), (3, (1, 6, 5)),
+                                   (3, (7, 1, 4)), (3, (1, 1, 7))])
+def test_forward_backward_vs_reference(gpu, dim, n):
+    """Network forward and gradients against the numpy reference, also on
+    one-cell-wide axes, where both patch neighbours along the axis are walls."""
     from oracle import mlp
-    inst = nn_instance(dim)
+    if n is None:
+        inst = nn_instance(dim)
+    elif dim == 2:
+        inst = I.strip_2d(n[0], n[1], 2, 8, 6, seed=7, strip_cells=1, nsteps=4)
+    else:
+        inst = I.gaussian_3d(*n, 2, 8, 6, seed=7, sigma_cells=1.0, precision=I.PRECISION_FP64,
+                             nsteps=4)
     Tn, Tp, E, Tx = synthetic_sample(inst, 11 + dim)
     norm = dict(muT=Tn.mean(), sT=Tn.std(), muE=E.mean(), sE=E.std(), sD=np.sqrt(np.mean((Tx - Tn) ** 2)))
     params = mlp.random_params(dim, seed=3 + dim)
