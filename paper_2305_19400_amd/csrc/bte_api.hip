@@ -194,9 +194,12 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   // direction groups and the kernel family (tuning knobs).  3D defaults: when
   // 64-column tiles would leave more than an eighth of the lanes idle (a
   // narrow mesh or a ragged last tile), the flattened (x, y) plane, with 4
-  // planes per wave for FP32 storage and 2 for FP64 storage (whose registers
-  // allow fewer waves); otherwise 2 rows x 2 planes per wave with FP64
-  // storage and 1 row x 4 planes with FP32 storage (the faster at 64^3).
+  // planes per wave for FP32 storage; with FP64 storage 4 planes once the
+  // 4-plane launch fills the device with a single direction group (4-5 %
+  // faster there) and 2 below that (whose registers allow more waves, and the
+  // extra tiles fewer direction groups); otherwise 2 rows x 2 planes per wave
+  // with FP64 storage and 1 row x 4 planes with FP32 storage (the faster at
+  // 64^3).
   const bool fp32 = o->precision != BTE_FP64;
   // The tiled kernels evaluate the FP32-storage update in the direct form
   // (I^n/dt + I0/tau + sum c I_up) * scale, which is the implicit Jacobi
@@ -209,7 +212,9 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
     const double lanes_used = (double)s.nx / (64.0 * ((s.nx + 63) / 64));
     if (lanes_used < 0.875) {
       kind_dflt = kSweepFlat3D;
-      rz_dflt = fp32 ? 4 : 2;
+      const long long tiles4 =
+          ((long long)s.nx * s.ny + 255) / 256 * ((s.nz + 3) / 4) * (long long)s.nb;
+      rz_dflt = (fp32 || tiles4 >= kSweepFillWorkgroups) ? 4 : 2;
     } else if (fp32) {
       ry_dflt = 1;
       rz_dflt = 4;

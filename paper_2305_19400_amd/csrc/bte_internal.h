@@ -21,6 +21,9 @@ constexpr int kSweepBlock = 256;     // threads per sweep workgroup (4 waves)
 constexpr int kCellBlock = 64;       // threads per per-cell kernel workgroup (one wave)
 constexpr int kReduceBlock = 256;    // threads of the single-workgroup reductions
 constexpr int kSlabAlign = 64;       // cells per slab rounded up to this
+// Sweep workgroups that fill a 256-CU device (about 32 per compute unit); the
+// default direction-group count of a sweep plan aims at this many.
+constexpr long long kSweepFillWorkgroups = 8192;
 // Temperature inversion: lanes per cell (each owns every lanes-th band entry)
 // and cells per 256-thread workgroup.  Four lanes where there are at most 32
 // band entries, eight above (measured: 2.5 % faster batches of 8-40 entries

@@ -269,15 +269,23 @@ def test_fp32_reaches_tight_tolerance(gpu, monkeypatch, dim, ry, rz):
 
 def test_default_layouts(gpu, monkeypatch):
     """Without overrides: the flattened plane where 64-column tiles would leave
-    lanes idle (4 planes with FP32 storage, 2 with FP64), the column walk where
-    x is a multiple of 64 (2 x 2 with FP64 storage, 1 x 4 with FP32)."""
+    lanes idle (4 planes with FP32 storage; with FP64, 4 once the 4-plane
+    launch has 8192 workgroups per direction group, else 2), the column walk
+    where x is a multiple of 64 (2 x 2 with FP64 storage, 1 x 4 with FP32)."""
     for name in ("BTE_SWEEP_KIND", "BTE_SWEEP_RY", "BTE_SWEEP_RZ", "BTE_SWEEP_NDG"):
         monkeypatch.delenv(name, raising=False)
-    narrow = case_3d_narrow()
-    full = I.gaussian_3d(64, 6, 5, 2, 8, 3, seed=57, precision=I.PRECISION_FP64, nsteps=1)
+    meshes = {
+        "narrow": case_3d_narrow(),
+        "full": I.gaussian_3d(64, 6, 5, 2, 8, 3, seed=57, precision=I.PRECISION_FP64, nsteps=1),
+        # 157 plane tiles x 2 blocks of 4 planes x 27 band entries = 8478 workgroups
+        "large": I.gaussian_3d(200, 200, 8, 2, 4, 20, seed=58, precision=I.PRECISION_FP64,
+                               nsteps=1),
+    }
+    assert meshes["large"].n_bands == 27
     want = {("narrow", gpu.BTE_FP64): (KIND_FLAT, 0, 2), ("narrow", gpu.BTE_FP32_MIXED): (KIND_FLAT, 0, 4),
-            ("full", gpu.BTE_FP64): (2, 2, 2), ("full", gpu.BTE_FP32_MIXED): (2, 1, 4)}
+            ("full", gpu.BTE_FP64): (2, 2, 2), ("full", gpu.BTE_FP32_MIXED): (2, 1, 4),
+            ("large", gpu.BTE_FP64): (KIND_FLAT, 0, 4)}
     for (which, prec), (kind, ry, rz) in want.items():
-        with gpu.Solver(narrow if which == "narrow" else full, precision=prec) as sol:
+        with gpu.Solver(meshes[which], precision=prec) as sol:
             lay = sol.sweep_layout()
         assert (lay["kind"], lay["ry"], lay["rz"]) == (kind, ry, rz), (which, prec, lay)
