@@ -118,7 +118,10 @@ typedef struct {
 } bte_dispersion;
 
 typedef struct {
-  double dt;            /* time step [s] > 0 */
+  double dt;            /* time step [s] > 0; with EXPLICIT_EULER at most
+                           1 / (1/tau_b + sum_a v_b |s_{d,a}| / h_a) for every band and
+                           direction (the step then keeps intensities positive and
+                           bounded; bte_create rejects a larger one with BTE_E_INVAL) */
   double tol;           /* inner stop: ||I^{k+1}-I^k|| <= tol ||I^{k+1}-I^n|| */
   int max_inner;        /* cap on inner sweeps per step (<= 0: 200) */
   int scheme;           /* bte_scheme */
@@ -150,7 +153,29 @@ typedef struct {
 /* Warm-start modes.  T: the first sweep of a step uses I0 at the guessed
  * temperature.  T_SHIFT: additionally starts the intensity from
  * I^n + I0_b(T_guess) - I0_b(T_n) (an isotropic shift), fused into the first
- * sweep. */
+ * sweep.
+ *
+ * The rules of the learned warm start (not in the paper):
+ *   - recording: each of the first nn_train_steps steps records, in FP32,
+ *     T_n, T_{n-1}, E_n at its start and T_{n+1} at its end (T_{n-1} = T_n
+ *     for the first step after create);
+ *   - normalisation, from every recorded sample: mu_T and s_T the mean and
+ *     population standard deviation of the T_n channel, mu_E and s_E those of
+ *     E_n, s_D the root mean square of T_{n+1} - T_n.  A non-positive variance
+ *     gives a scale of 1; a T or E scale at or below 1e-6 |mean| becomes
+ *     1e-6 |mean| + 1e-30; a zero s_D becomes 1;
+ *   - training order: N = nn_train_steps x N_c samples, sample i = step
+ *     i / N_c, cell i % N_c.  Position p of epoch e takes sample
+ *     (a p + c_e) mod N with a = floor(0.6180339887 N) | 1, raised by 2 until
+ *     gcd(a, N) = 1, and c_e = 7919 e mod N; minibatches are 8192 consecutive
+ *     positions (the last one of an epoch shorter);
+ *   - loss: mean over the minibatch of (y - (T_{n+1} - T_n)/s_D)^2;
+ *   - Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, FP32 masters and
+ *     moments) on every weight and bias; the zero-padded feature columns of W1
+ *     stay zero;
+ *   - use: guess = T_n + s_D y per cell; it is rejected (the cell starts from
+ *     T_n and counts as a fallback) unless s_D y is finite, at most
+ *     10 max(s_D, |T_n - T_{n-1}|) in size, and the guess is positive. */
 enum bte_warm { BTE_WARM_NONE = 0, BTE_WARM_T = 1, BTE_WARM_T_SHIFT = 2 };
 
 typedef struct {
@@ -192,10 +217,64 @@ int bte_intensity(bte_ctx* ctx, double* I_out, size_t n);
 /* Copies the per-cell energy density E_P = sum_b sum_d w_d I_{d,b,P} [N_c]. */
 int bte_energy(bte_ctx* ctx, double* E_out, size_t n_cells);
 
-/* Replaces the state: intensity (host, FP64, [band][direction][cell]) and
- * temperature [N_c] (each > 0).  The temperature must be consistent with the
- * intensity for the result to be meaningful (it seeds the next inversion). */
-int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size_t n_cells);
+/* Replaces the intensity (host, FP64, [band][direction][cell]) and the
+ * temperature [N_c] (each > 0) of the current time level; the energy density
+ * is recomputed from the intensity and the previous time level's temperature
+ * is set to the given one.  The temperature must be consistent with the
+ * intensity for the result to be meaningful (it seeds the next inversion).
+ * To resume a run exactly, use bte_get_state / bte_set_state. */
+int bte_set_fields(bte_ctx* ctx, const double* I, size_t n, const double* T, size_t n_cells);
+
+/* Checkpoint of everything the next steps depend on: the intensity of the
+ * current time level in storage format, T_n, T_{n-1}, the energy density, the
+ * equilibrium intensities, the storage reference, the sweep layout, the step
+ * count, and with a learned warm start its recorded training history, the
+ * sweeps of the recorded steps, its parameters, Adam moments and step count,
+ * and the guard counters.  A context created from the same inputs and
+ * options that restores it continues bit for bit as the saved context would
+ * have (the sweep layout is restored with it where the context can hold it;
+ * otherwise results agree to rounding).
+ *
+ * Layout of the state bytes: this header, then the sections at the byte
+ * offsets off[] (each 256-byte aligned; 0 = absent):
+ *   off[0] intensity [band][direction][cell], FP64 (BTE_FP64) or the FP32
+ *          deviation from the storage reference (BTE_FP32_MIXED);
+ *   off[1] T_n, off[2] T_{n-1}, off[3] E_n: FP64 [N_c] each;
+ *   off[4] I0_b(T_n): FP64 [band][cell];  off[5] storage reference: FP64 [band];
+ *   off[6] inner sweeps of each recorded plain step: int32 [nn_rec];
+ *   off[7] parameters, off[8] Adam first moments, off[9] Adam second
+ *          moments: FP32 [nn_params] each;
+ *   off[10] recorded history: FP32 [nn_rec][4][N_c], channels T_n, T_{n-1},
+ *          E_n, T_{n+1} (the first nn_recorded steps are valid). */
+typedef struct {
+  char magic[8];       /* "BTESTAT1" */
+  int version;         /* 1 */
+  int header_bytes;    /* sizeof(bte_state_header) */
+  int dim, n[3], nd, nb;
+  int precision, scheme, warm_start, nn_rec;
+  int layout[4];       /* sweep layout: kind, rows, planes, direction groups */
+  long long steps;     /* time steps taken since create */
+  int nn_recorded;     /* plain steps recorded for training */
+  int nn_trained;      /* network trained (or parameters set) */
+  int nn_off;          /* guess switched off by the guard */
+  int nn_warm_steps, nn_warm_sweeps;  /* guard window so far */
+  int nn_adam_t;       /* Adam updates taken */
+  int nn_last_batch;   /* samples of the last minibatch */
+  int nn_params;       /* parameter count (0 without a warm start) */
+  unsigned long long off[11];
+  unsigned long long total;  /* bytes of the whole state */
+} bte_state_header;
+
+/* Bytes of the state of this context. */
+int bte_state_size(bte_ctx* ctx, size_t* bytes);
+/* Writes the state into host memory buf of at least bte_state_size() bytes
+ * (waits for the context's stream). */
+int bte_get_state(bte_ctx* ctx, void* buf, size_t bytes);
+/* Restores a state written by bte_get_state.  BTE_E_STATE if it was taken
+ * from a context of another shape, precision, scheme, warm-start mode,
+ * recording length or storage reference, or is truncated; the context is
+ * then untouched. */
+int bte_set_state(bte_ctx* ctx, const void* buf, size_t bytes);
 
 /* Sum and count of the sweep-kernel durations measured since the last call
  * (options.timing must be set); resets the accumulators. */

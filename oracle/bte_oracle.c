@@ -429,10 +429,21 @@ static double total_energy(const oracle_bte* o) {
   return tot;
 }
 
-int oracle_step(oracle_bte* o, int fixed_inner, oracle_stats* st) {
+/* One time step from the starting temperature T0 (NULL: T_n).  With shift,
+ * the starting iterate is I^n + I0_b(T0) - I0_b(T_n) (an isotropic shift of
+ * every direction); the increment norm's denominator still uses I^n. */
+static int step_from(oracle_bte* o, int fixed_inner, const double* T0, int shift,
+                     oracle_stats* st) {
   size_t ndof = (size_t)o->nc * o->nd * o->nb;
   memcpy(o->Ik, o->In, sizeof(double) * ndof);
-  memcpy(o->Tk, o->Tn, sizeof(double) * o->nc);
+  memcpy(o->Tk, T0 ? T0 : o->Tn, sizeof(double) * o->nc);
+  if (T0 && shift) {
+    for (int P = 0; P < o->nc; ++P)
+      for (int b = 0; b < o->nb; ++b) {
+        double dI = oracle_equilibrium(o, b, T0[P]) - oracle_equilibrium(o, b, o->Tn[P]);
+        for (int d = 0; d < o->nd; ++d) o->Ik[idx(o, P, d, b)] += dI;
+      }
+  }
   o->failed_cell = -1;
   int k = 0, newton_max = 0;
   double res = 0.0;
@@ -490,6 +501,18 @@ void oracle_get_E(const oracle_bte* o, double* E, double* G) {
     if (E) E[P] = e;
     if (G) G[P] = g;
   }
+}
+
+int oracle_step(oracle_bte* o, int fixed_inner, oracle_stats* st) {
+  return step_from(o, fixed_inner, NULL, 0, st);
+}
+
+int oracle_step_warm(oracle_bte* o, int fixed_inner, const double* T0, int shift,
+                     oracle_stats* st) {
+  if (!T0) return ORACLE_E_INVAL;
+  for (int P = 0; P < o->nc; ++P)
+    if (!(T0[P] > 0.0)) return ORACLE_E_INVAL;
+  return step_from(o, fixed_inner, T0, shift, st);
 }
 
 int oracle_set_state(oracle_bte* o, const double* I, const double* T) {

@@ -72,6 +72,15 @@ void oracle_destroy(oracle_bte* o);
  * (replaying another solver's schedule); 0 stops on tol / max_inner. */
 int oracle_step(oracle_bte* o, int fixed_inner, oracle_stats* st);
 
+/* One implicit time step seeded with a starting temperature T0 [N_c] (a
+ * warm start of the inner iteration): the first sweep takes T^(0) = T0 and
+ * I0_b(T0); with shift != 0 its starting iterate is also moved by the
+ * isotropic equilibrium difference I0_b(T0) - I0_b(T_n).  The iteration and its
+ * stopping rule are those of oracle_step, so only the route to the fixed point
+ * changes. */
+int oracle_step_warm(oracle_bte* o, int fixed_inner, const double* T0, int shift,
+                     oracle_stats* st);
+
 void oracle_get_T(const oracle_bte* o, double* T);          /* [N_c] */
 void oracle_get_I(const oracle_bte* o, double* I);          /* [N_c][N_d][N_b] */
 void oracle_get_E(const oracle_bte* o, double* E, double* G); /* [N_c] each, may be NULL */

@@ -145,3 +145,168 @@ def unpack(vec, dim):
     nm = take(8)
     return (dict(W1=W1, b1=b1, W2=W2, b2=b2, w3=w3, b3=b3),
             dict(muT=nm[0], sT=nm[1], muE=nm[2], sE=nm[3], sD=nm[4]))
+
+
+# ---------------------------------------------------------------- training and use
+# The steps below follow the warm-start rules the library documents (they are
+# not in the paper): recorded samples, normalisation, the minibatch order, Adam
+# and the plausibility test of a guess.  FP64 arithmetic; with emulate=True
+# the FP32 storage points of the library (recorded fields, normalisation
+# constants, master parameters and Adam moments) are rounded to float32.
+
+ADAM_BETA1 = 0.9
+ADAM_BETA2 = 0.999
+ADAM_EPS = 1e-8
+BATCH = 8192  # minibatch size
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def normalisation(hist):
+    """Normalisation constants of a recorded history hist[step][4][N_c]
+    (channels T_n, T_{n-1}, E_n, T_{n+1}): mean and population standard
+    deviation of the T_n channel and of the E_n channel over every recorded
+    sample, and the root mean square of T_{n+1} - T_n.  A non-positive
+    variance gives a scale of 1; a T or E scale at or below 1e-6 |mean| is
+    raised to 1e-6 |mean| + 1e-30; a zero RMS change gives 1."""
+    h = np.asarray(hist, dtype=np.float64)
+    t, e = h[:, 0, :].ravel(), h[:, 2, :].ravel()
+    d = (h[:, 3, :] - h[:, 0, :]).ravel()
+    muT, muE = t.mean(), e.mean()
+    vT, vE = np.mean((t - muT) ** 2), np.mean((e - muE) ** 2)
+    sD = np.sqrt(np.mean(d * d))
+    sT = np.sqrt(vT) if vT > 0 else 1.0
+    sE = np.sqrt(vE) if vE > 0 else 1.0
+    sT, sE, muT32, muE32 = float(np.float32(sT)), float(np.float32(sE)), float(np.float32(muT)), float(np.float32(muE))
+    if not sT > 1e-6 * abs(muT32):
+        sT = float(np.float32(np.float32(1e-6) * np.float32(abs(muT32)) + np.float32(1e-30)))
+    if not sE > 1e-6 * abs(muE32):
+        sE = float(np.float32(np.float32(1e-6) * np.float32(abs(muE32)) + np.float32(1e-30)))
+    return dict(muT=muT32, sT=sT, muE=muE32, sE=sE, sD=float(np.float32(sD if sD > 0 else 1.0)))
+
+
+def schedule(nsamples, epochs=0):
+    """Minibatch order of one training: sample position i of an epoch maps to
+    recorded sample (a i + c_e) mod N, a = floor(0.6180339887 N) | 1 raised by 2
+    until gcd(a, N) = 1, c_e = 7919 e mod N; each epoch is cut into minibatches
+    of BATCH consecutive positions; epochs <= 0 means max(2, ceil(300 /
+    minibatches per epoch)).  Returns (a, [(first position, c_e, size), ...])."""
+    from math import gcd
+    N = int(nsamples)
+    a = int(0.6180339887 * float(N)) | 1
+    while gcd(a, N) != 1:
+        a += 2
+    per_epoch = (N + BATCH - 1) // BATCH
+    if epochs <= 0:
+        epochs = max(2, (300 + per_epoch - 1) // per_epoch)
+    ups = []
+    for e in range(epochs):
+        c = (e * 7919) % N
+        for b0 in range(0, N, BATCH):
+            ups.append((b0, c, min(BATCH, N - b0)))
+    return a, ups
+
+
+def adam_step(p, g, m, v, t, lr, trainable=None):
+    """One Adam update (Kingma and Ba 2015, Algorithm 1) with beta1 0.9, beta2
+    0.999, eps 1e-8 and bias correction at step t >= 1; entries outside
+    `trainable` keep their parameter and moments."""
+    m_new = ADAM_BETA1 * m + (1.0 - ADAM_BETA1) * g
+    v_new = ADAM_BETA2 * v + (1.0 - ADAM_BETA2) * g * g
+    mhat = m_new / (1.0 - ADAM_BETA1 ** t)
+    vhat = v_new / (1.0 - ADAM_BETA2 ** t)
+    p_new = p - lr * mhat / (np.sqrt(vhat) + ADAM_EPS)
+    if trainable is not None:
+        p_new = np.where(trainable, p_new, p)
+        m_new = np.where(trainable, m_new, m)
+        v_new = np.where(trainable, v_new, v)
+    return p_new, m_new, v_new
+
+
+def trainable_mask(dim):
+    """Entries of the flat parameter vector that training updates: every weight
+    and bias except the zero-padded feature columns of W1, the padding after b3
+    and the normalisation constants."""
+    k, kp = n_features(dim), padded_features(dim)
+    W1 = np.zeros((HIDDEN, kp), dtype=bool)
+    W1[:, :k] = True
+    parts = [W1.ravel(), np.ones(HIDDEN, bool), np.ones(HIDDEN * HIDDEN, bool),
+             np.ones(HIDDEN, bool), np.ones(HIDDEN, bool), np.array([True, False, False, False]),
+             np.zeros(8, bool)]
+    return np.concatenate(parts)
+
+
+def _flat_to_params(vec, dim):
+    params, _ = unpack(vec, dim)
+    return params
+
+
+def _grad_to_flat(g, dim):
+    return np.concatenate([g["W1"].ravel(), g["b1"], g["W2"].ravel(), g["b2"], g["w3"],
+                           np.array([g["b3"][0], 0.0, 0.0, 0.0]), np.zeros(8)])
+
+
+def minibatch(hist, n, dim, norm, a, b0, c, size):
+    """Features and targets of one minibatch: positions b0 .. b0+size-1 of the
+    permuted order, sample i = (a pos + c) mod N = step i // N_c, cell i % N_c."""
+    h = np.asarray(hist, dtype=np.float64)
+    nrec, _, nc = h.shape
+    N = nrec * nc
+    pos = np.arange(b0, b0 + size, dtype=np.int64)
+    idx = (a * pos + c) % N
+    steps, cells = idx // nc, idx % nc
+    X = np.empty((size, n_features(dim)))
+    for st in np.unique(steps):
+        sel = steps == st
+        Xs = gather(n, dim, h[st, 0], h[st, 1], h[st, 2], norm)
+        X[sel] = Xs[cells[sel]]
+    t = (h[steps, 3, cells] - h[steps, 0, cells]) / norm["sD"]
+    return X, t
+
+
+def train(vec0, hist, n, dim, epochs=0, lr=1e-3, emulate=True, t0=0, m0=None, v0=None):
+    """Replays one training of the warm-start network from the flat parameter
+    vector vec0 on the recorded history hist[step][4][N_c]: normalisation, then
+    one Adam update per minibatch of the schedule on the mean squared error.
+    Returns (parameter vector, m, v, Adam step count, per-update losses)."""
+    r32 = f32 if emulate else (lambda x: np.asarray(x, dtype=np.float64))
+    norm = normalisation(hist)
+    P = np.asarray(vec0, dtype=np.float64).copy()
+    ko = padded_features(dim) * HIDDEN + HIDDEN * HIDDEN + 3 * HIDDEN + 4  # norm offset
+    P[ko:ko + 5] = [norm["muT"], norm["sT"], norm["muE"], norm["sE"], norm["sD"]]
+    P[ko + 5:] = 0.0
+    m = np.zeros_like(P) if m0 is None else np.asarray(m0, dtype=np.float64).copy()
+    v = np.zeros_like(P) if v0 is None else np.asarray(v0, dtype=np.float64).copy()
+    mask = trainable_mask(dim)
+    h = np.asarray(hist, dtype=np.float64)
+    a, ups = schedule(h.shape[0] * h.shape[2], epochs)
+    t = t0
+    losses = []
+    for b0, c, size in ups:
+        X, tgt = minibatch(h, n, dim, norm, a, b0, c, size)
+        if emulate:
+            X, tgt = f32(X), f32(tgt)
+        params = _flat_to_params(P, dim)
+        loss, g = loss_and_grad(params, pad_features(X, dim), tgt, emulate_bf16=emulate)
+        gf = _grad_to_flat(g, dim)
+        t += 1
+        P, m, v = adam_step(P, gf, m, v, t, lr, mask)
+        P, m, v = r32(P), r32(m), r32(v)
+        losses.append(loss)
+    return P, m, v, t, losses
+
+
+def accept_guess(Tn, Tprev, y, sD, max_step=10.0):
+    """Plausibility test of a warm-start guess T_n + s_D y per cell: kept if the
+    change is finite, at most max_step * max(s_D, |T_n - T_{n-1}|) in size and
+    the guess is positive; otherwise the cell starts from T_n.  Returns the
+    starting temperature and the mask of rejected cells."""
+    Tn = np.asarray(Tn, dtype=np.float64)
+    dT = float(sD) * np.asarray(y, dtype=np.float64)
+    lim = max_step * np.maximum(float(sD), np.abs(Tn - np.asarray(Tprev, dtype=np.float64)))
+    with np.errstate(invalid="ignore"):
+        T0 = Tn + dT
+        bad = ~np.isfinite(dT) | (np.abs(dT) > lim) | ~(T0 > 0.0)
+    return np.where(bad, Tn, T0), bad

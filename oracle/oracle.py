@@ -63,6 +63,7 @@ def _load():
                                   C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_int]
     lib.oracle_destroy.argtypes = [C.c_void_p]
     lib.oracle_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(_Stats)]
+    lib.oracle_step_warm.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(_Stats)]
     lib.oracle_get_T.argtypes = [C.c_void_p, _dp]
     lib.oracle_get_I.argtypes = [C.c_void_p, _dp]
     lib.oracle_get_E.argtypes = [C.c_void_p, _dp, _dp]
@@ -140,6 +141,20 @@ class Oracle:
         rc = self.lib.oracle_step(self._h, int(fixed_inner), C.byref(st))
         if rc != 0:
             raise OracleError(f"oracle_step failed ({rc}), cell {self.lib.oracle_failed_cell(self._h)}")
+        return dict(inner=st.inner, res=st.res, newton_max=st.newton_max, energy=st.energy)
+
+    def step_warm(self, T0, shift: bool = False, fixed_inner: int = 0):
+        """One implicit step whose inner iteration starts from temperature T0
+        (and, with shift, from I^n moved by I0_b(T0) - I0_b(T_n))."""
+        T0 = np.ascontiguousarray(T0, dtype=np.float64).reshape(-1)
+        if T0.size != self.nc:
+            raise OracleError("T0 size mismatch")
+        st = _Stats()
+        rc = self.lib.oracle_step_warm(self._h, int(fixed_inner), _ptr(T0), int(bool(shift)),
+                                       C.byref(st))
+        if rc != 0:
+            raise OracleError(f"oracle_step_warm failed ({rc}), cell "
+                              f"{self.lib.oracle_failed_cell(self._h)}")
         return dict(inner=st.inner, res=st.res, newton_max=st.newton_max, energy=st.energy)
 
     def run(self, nsteps: int, schedule=None):

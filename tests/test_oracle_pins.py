@@ -481,3 +481,38 @@ def test_diffusive_limit_fourier():
         assert abs(r - 1.0) < 0.10
     assert abs((2 * r20 - r10) - 1.0) < 0.01
     assert r20 < r10  # the discretisation error shrinks with h / Lambda
+
+
+# ---------------------------------------------------------------- warm-started step
+@pytest.mark.parametrize("shift", [False, True])
+def test_warm_step_from_current_temperature_is_the_plain_step(shift):
+    """Seeding the inner iteration with T^(0) = T_n (and so a zero shift) is the
+    plain step, bit for bit."""
+    inst = tiny_2d(seed=21, n=(5, 4))
+    a, b = Oracle(inst), Oracle(inst)
+    a.step()
+    b.step()
+    sa = a.step()
+    sb = b.step_warm(b.temperature(), shift=shift)
+    assert sa == sb
+    assert np.array_equal(a.temperature(), b.temperature())
+    assert np.array_equal(a.intensity(), b.intensity())
+
+
+@pytest.mark.parametrize("maker", [tiny_2d, tiny_3d])
+@pytest.mark.parametrize("shift", [False, True])
+def test_warm_step_reaches_the_same_fixed_point(maker, shift):
+    """The backward-Euler system has one solution, so a step run to a tight
+    tolerance lands on it from any starting temperature; only the route
+    (and the sweep count) changes."""
+    inst = maker()
+    a = Oracle(inst, tol=1e-13)
+    b = Oracle(inst, tol=1e-13)
+    rng = np.random.default_rng(5)
+    T0 = inst.T_init + rng.uniform(-3.0, 3.0, inst.T_init.shape)
+    a.step()
+    b.step_warm(T0, shift=shift)
+    assert rel(b.temperature(), a.temperature()) <= 1e-12
+    assert rel(b.intensity(), a.intensity()) <= 1e-11
+    with pytest.raises(OracleError):
+        b.step_warm(-T0)
