@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the phonon BTE time step on one MI355X.
 
-Workload: 2D 128 x 128 cells, 400 directions (20 polar x 20 azimuthal),
-55 band entries (40 frequency bands, 15 of them with a transverse branch),
-strip heater on the top wall, implicit backward-Euler steps of 1 ps with
-point-Jacobi inner sweeps to a 1e-4 step-relative residual, FP64.  A "step" is
-one time step: every inner sweep, energy reduction, temperature inversion and
-convergence test of that step.  Inputs are seeded and synthetic (Si-like band
-tables), resident in HBM before timing starts.
+Default workload (c2): 2D 128 x 128 cells, 400 directions (20 polar x 20
+azimuthal), 55 band entries (40 frequency bands, 15 of them with a transverse
+branch), strip heater on the top wall, implicit backward-Euler steps of 1 ps
+with point-Jacobi inner sweeps to a 1e-4 step-relative residual, FP64.  A
+"step" is one time step: every inner sweep, energy reduction, temperature
+inversion and convergence test of that step.  Inputs are seeded and synthetic
+(Si-like band tables), resident in HBM before timing starts.
 
-Prints one JSON line on stdout; progress goes to stderr.
+Other workloads: c1 (16 x 16, 16 directions, 4 bands), c3 / c4 (64^3 / 96^3,
+400 x 55, FP32 storage), c5 (64 uneven geometries batched), f1 (the paper's
+own demonstration: 120 x 120, 20 directions x 55 entries, forward Euler).
+
+Prints one JSON line on stdout; progress goes to stderr, every line stamped
+with the seconds since start.
 """
 import argparse
 import json
@@ -24,15 +29,32 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+T_START = time.perf_counter()
+
+
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.perf_counter() - T_START:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+# The paper's only speed figure, with the hardware and workload it is quoted on
+# (context, not the target: another machine, another scheme and path).
+PAPER_CONTEXT = {
+    "paper_speedup": 18.0,
+    "what": "GPU build vs the same DSL's CPU-only build with an equal number of partitions",
+    "gpu": "NVIDIA A6000 (A100 gave similar results)",
+    "cpu": "two-socket Intel Xeon Scalable (Cascade Lake) nodes, 40 cores, 192 GB",
+    "precision": "FP64",
+    "workload": "2D 120 x 120 cells, 20 directions x 55 band entries (~1.6e7 DOF), "
+                "forward Euler, 100 steps",
+    "source": "paper Abstract and Sec. 3.4 (GPU results)",
+}
 
 
 def sweep_bytes(inst, real_bytes):
     """Algorithmic HBM bytes of one sweep launch: read I^k and I^n, write I^{k+1}
-    for every (cell, direction, band), plus per-(band, cell) equilibrium read
-    and energy-partial write."""
-    per_update = 3 * real_bytes
+    for every (cell, direction, band) (forward Euler: read I^n, write I^{n+1}),
+    plus per-(band, cell) equilibrium read and energy-partial write."""
+    per_update = (2 if inst.scheme == 1 else 3) * real_bytes
     per_band_cell = 8 + 8
     return inst.n_dof * per_update + inst.n_bands * inst.n_cells * per_band_cell
 
@@ -53,21 +75,29 @@ def measured_traffic(kernel_file, counters_file):
     return c.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(inst, log_fn):
-    """Oracle (plain FP64 C, OpenMP over cells) on the host cores: the first
-    time step of the same workload, all of its inner sweeps."""
+def cpu_baseline(inst, log_fn, budget_s=10.0):
+    """Oracle (plain FP64 C, OpenMP over cells) on the host cores: time steps
+    of the same workload from its initial state, every inner sweep, until
+    about ``budget_s`` seconds have passed (at least one step, at most the
+    workload's own step count); plus one sweep on one thread."""
     from oracle import Oracle
     from oracle import oracle as om
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = int(os.environ.get("OMP_NUM_THREADS", threads))
     om.set_threads(threads)
-    log_fn(f"cpu baseline: oracle, first time step of {inst.name}, {threads} threads")
+    log_fn(f"cpu baseline: oracle time steps of {inst.name}, {threads} threads")
     o = Oracle(inst)
     t0 = time.perf_counter()
-    st = o.step()
+    sweeps, nsteps = 0, 0
+    while True:
+        sweeps += o.step()["inner"]
+        nsteps += 1
+        if time.perf_counter() - t0 >= budget_s or nsteps >= max(1, inst.nsteps):
+            break
     dt = time.perf_counter() - t0
-    updates = st["inner"] * inst.n_dof
+    updates = sweeps * inst.n_dof
     del o
+    log_fn(f"cpu baseline: {nsteps} steps, {sweeps} sweeps in {dt:.1f} s; one-thread sweep")
     # one thread: a single sweep of a fresh first step (bounded sample)
     om.set_threads(1)
     o1 = Oracle(inst)
@@ -84,7 +114,7 @@ def cpu_baseline(inst, log_fn):
     return {"value": updates / dt, "unit": "updates/s", "cores": threads,
             "kind": "oracle", "cpu_model": model,
             "one_thread_value": inst.n_dof / dt1,
-            "sample": f"first time step of {inst.name} ({st['inner']} inner sweeps, "
+            "sample": f"first {nsteps} time steps of {inst.name} ({sweeps} inner sweeps, "
                       f"{updates:.3e} updates) in {dt:.1f} s on {threads} threads; one thread: "
                       f"one sweep ({inst.n_dof:.3e} updates) in {dt1:.1f} s"}
 
@@ -104,24 +134,35 @@ def copy_probe():
 
 def run_solo(bte, inst, prec, steps, label, timing=False, **opts):
     """Steps one fresh context ``steps`` times; returns wall time, per-step stats,
-    final temperature and (with timing) the sweep-kernel time."""
+    final temperature and (with timing) the sweep-kernel time.  Logs the
+    context's creation, every 10 steps (every step once steps take over a
+    second), the network's training and the close."""
     import torch
+    log(f"{label}: creating context")
     sol = bte.Solver(inst, device="cuda:0", precision=prec, timing=timing, **opts)
     torch.cuda.synchronize()
+    log(f"{label}: context ready ({sol.workspace_bytes / 1e9:.1f} GB workspace)")
     sol.sweep_time()  # reset accumulators
     t0 = time.perf_counter()
-    stats, done = [], 0
+    stats, done, chunk = [], 0, 10
     while done < steps:
-        n = min(10, steps - done)
-        stats += sol.step(n)
+        n = min(chunk, steps - done)
+        c0 = time.perf_counter()
+        new = sol.step(n)
+        stats += new
         done += n
+        if any(s["trained"] for s in new):
+            log(f"{label}: network trained (loss {[s['nn_loss'] for s in new if s['trained']][0]:.3e})")
         log(f"{label}: steps {done}/{steps}, inner last={stats[-1]['inner']}")
+        if (time.perf_counter() - c0) / n > 1.0:
+            chunk = 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sweep_ms, nsweeps = sol.sweep_time()
     T = sol.temperature()
     layout = sol.sweep_layout()
     sol.close()
+    log(f"{label}: closed")
     return {"wall": wall, "stats": stats, "T": T, "sweep_ms": sweep_ms, "nsweeps": nsweeps,
             "layout": layout}
 
@@ -145,6 +186,7 @@ def loosest_accurate(bte, inst, steps, prec, T_ref, label, **opts):
     import numpy as np
     tried = []
     for tol in TTS_LADDER:
+        log(f"time to solution: {label} at inner tolerance {tol:g}")
         r = run_solo(bte, inst, prec, steps, f"{label} tol={tol:g}", tol=tol, **opts)
         err = max_rel(r["T"], T_ref)
         rise = float(np.max(np.abs(r["T"] - T_ref)) / max(float(np.max(T_ref)) - 300.0, 1e-300))
@@ -209,9 +251,11 @@ def run_c5(args):
                        warm_start=bte.BTE_WARM_T, nn_train_steps=train, nn_seed=inst.seed)
         s.autotune(cache, batch=True)
         sols.append(s)
-        if (k + 1) % 16 == 0:
-            log(f"c5: {k + 1} contexts created")
+        if (k + 1) % 4 == 0:
+            log(f"c5: {k + 1} contexts created and tuned")
+    log("c5: creating the batch (work lists, captured iteration)")
     batch = bte.Batch(sols, use_graph=True)
+    log("c5: batch ready")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     per_step, done = [], 0
@@ -274,20 +318,43 @@ def run_c5(args):
     print(json.dumps(out), flush=True)
 
 
+# Per workload: default storage precision, default timed steps, whether the
+# FP64 state fits one GPU (the time-to-solution reference and baseline).
+WORKLOADS = {
+    "c1": dict(precision="fp64", steps=50, fp64_fits=True),
+    "c2": dict(precision="fp64", steps=200, fp64_fits=True),
+    "c3": dict(precision="fp32", steps=100, fp64_fits=True),
+    "c4": dict(precision="fp32", steps=100, fp64_fits=False),
+    "f1": dict(precision="fp64", steps=100, fp64_fits=True),
+}
+
+# committed rocprofv3 counter summaries, by workload and storage precision
+COUNTERS = {("c2", "fp64"): "sweep2d_c2_fp64_counters.json",
+            ("c2", "fp32"): "sweep2d_c2_fp32_counters.json",
+            ("c3", "fp64"): "sweep3d_c3_fp64_counters.json",
+            ("c3", "fp32"): "sweep3d_c3_fp32_counters.json",
+            ("c4", "fp32"): "sweep3d_c4_fp32_counters.json"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="time steps (default 200; 30 for c5)")
+                    help="timed time steps (default: the workload's own count; 20 for c5)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
-                    help="fp64 (default) or fp32 storage; c4 defaults to fp32, since its "
-                         "FP64 state does not fit in one GPU's memory")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
-                    help="c2 (default, the benchmarked 2D case), the 3D cases, or the batch")
+                    help="storage precision (default: the workload's own: fp32 for c3 and c4, "
+                         "else fp64)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5", "f1"], default="c2",
+                    help="c2 (default, the benchmarked 2D case), c1, the 3D cases c3 / c4, "
+                         "the batch c5, or the paper's demonstration f1")
     ap.add_argument("--no-tts", action="store_true",
-                    help="skip the FP32 + learned warm start time-to-solution comparison")
+                    help="skip the time-to-solution comparison (FP64 plain vs FP32 + learned "
+                         "warm start)")
+    ap.add_argument("--tts-steps", type=int, default=None,
+                    help="time steps of the time-to-solution runs (default: the workload's own "
+                         "count, whatever --steps is)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -301,22 +368,27 @@ def main():
     if args.workload == "c5":
         run_c5(args)
         return
+    wl = WORKLOADS[args.workload]
     if args.steps is None:
-        args.steps = 200
+        args.steps = wl["steps"]
     if args.precision is None:
-        args.precision = "fp32" if args.workload == "c4" else "fp64"
+        args.precision = wl["precision"]
 
+    log("loading torch and the library")
     import torch
     from paper_2305_19400_amd import bte, inputs
+    bte.load_library()
 
     inst = inputs.CONFIGS[args.workload]()
+    explicit = inst.scheme == inputs.SCHEME_EXPLICIT_EULER
     prec = bte.BTE_FP64 if args.precision == "fp64" else bte.BTE_FP32_MIXED
     real_bytes = 8 if prec == bte.BTE_FP64 else 4
-    dev = torch.device("cuda:0")
     log(f"workload {inst.name}: {inst.n} cells, {inst.n_dirs} dirs, {inst.n_bands} bands, "
-        f"N_dof={inst.n_dof:.3e}, precision={args.precision}")
+        f"N_dof={inst.n_dof:.3e}, precision={args.precision}, "
+        f"{'explicit' if explicit else 'implicit'}")
 
     if args.warmup > 0:
+        log(f"warmup: {args.warmup} steps on a separate context")
         with bte.Solver(inst, device="cuda:0", precision=prec) as sol:
             sol.step(args.warmup)
         log(f"warmup: {args.warmup} steps done")
@@ -330,7 +402,8 @@ def main():
     avg_sweep_s = sweep_ms / 1e3 / max(nsweeps, 1)
     achieved = sweep_bytes(inst, real_bytes) / avg_sweep_s / 1e9
     out = {
-        "metric": "cell-dir-band updates/s (implicit point-Jacobi sweeps)",
+        "metric": ("cell-dir-band updates/s (forward-Euler steps)" if explicit else
+                   "cell-dir-band updates/s (implicit point-Jacobi sweeps)"),
         "value": updates / wall,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -342,11 +415,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == bte.BTE_FP64 else "f32+f64",
         "data": ("synthetic (seeded Si-like band tables, "
-                 + ("strip heater)" if inst.dim == 2 else "Gaussian hot spot)")),
+                 + ("Gaussian hot spot on one wall)" if args.workload == "f1" else
+                    "strip heater)" if inst.dim == 2 else "Gaussian hot spot)")),
         "config": {"workload": inst.name, "mesh": "x".join(str(v) for v in inst.n[:inst.dim]),
-                   "dirs": inst.n_dirs,
-                   "bands": inst.n_bands, "dt_s": inst.dt, "tol": inst.tol,
-                   "scheme": "implicit backward Euler, point-Jacobi",
+                   "cell_m": inst.h[0], "dirs": inst.n_dirs, "bands": inst.n_bands,
+                   "dt_s": inst.dt, "tol": None if explicit else inst.tol,
+                   "scheme": ("forward Euler" if explicit else
+                              "implicit backward Euler, point-Jacobi"),
                    "time_steps": args.steps},
         "time_to_solution_s": wall,
         "inner_sweeps": sweeps,
@@ -359,19 +434,31 @@ def main():
                      "layout": main_run["layout"],
                      "avg_ms": avg_sweep_s * 1e3,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
+        "paper_context": dict(PAPER_CONTEXT),
     }
-    # committed rocprofv3 counter summaries, by workload and storage precision
-    counters = {("c2", "fp64"): "sweep2d_c2_fp64_counters.json",
-                ("c3", "fp64"): "sweep3d_c3_fp64_counters.json",
-                ("c4", "fp32"): "sweep3d_c4_fp32_counters.json"}
     key = (args.workload, args.precision)
-    if key in counters:
+    if key in COUNTERS:
         out["roofline"]["traffic"] = measured_traffic(
             os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
-            os.path.join(ROOT, "profiles", counters[key]))
-    if not args.no_tts and args.steps > 20:
-        out["time_to_solution"] = time_to_solution(bte, inst, args.steps, prec)
-    if not args.no_cpu_baseline and args.workload == "c2":
+            os.path.join(ROOT, "profiles", COUNTERS[key]))
+    if prec == bte.BTE_FP32_MIXED and wl["fp64_fits"]:
+        # the FP32 result's error against FP64 storage at the same tolerance
+        torch.cuda.empty_cache()
+        r64 = run_solo(bte, inst, bte.BTE_FP64, args.steps, "fp64 at the same tolerance")
+        torch.cuda.empty_cache()
+        out["T_error_vs_fp64"] = {
+            "max_rel": max_rel(T, r64["T"]),
+            "of_rise": float(abs(T - r64["T"]).max() / max(float(r64["T"].max()) - 300.0, 1e-300)),
+            "fp64_s": r64["wall"], "fp64_sweeps": sum(x["inner"] for x in r64["stats"])}
+    if not args.no_tts and not explicit:
+        tts_steps = args.tts_steps if args.tts_steps is not None else wl["steps"]
+        torch.cuda.empty_cache()
+        base = bte.BTE_FP64 if wl["fp64_fits"] else bte.BTE_FP32_MIXED
+        log(f"time to solution: {tts_steps} steps, baseline "
+            f"{'fp64' if base == bte.BTE_FP64 else 'fp32'} plain")
+        tts = time_to_solution(bte, inst, tts_steps, base)
+        out["time_to_solution"] = dict(tts, steps=tts_steps)
+    if not args.no_cpu_baseline and args.workload in ("c1", "c2", "f1"):
         out["cpu_baseline"] = cpu_baseline(inst, log)
     elif not args.no_cpu_baseline and args.workload in ("c3", "c4"):
         # the oracle's FP64 state of the full mesh (138 / 467 GB) is out of
@@ -384,6 +471,9 @@ def main():
         cb["sample"] += ("; per-update rate taken to hold at the full mesh (the oracle "
                          "streams the same per-slab work)")
         out["cpu_baseline"] = cb
+    if "cpu_baseline" in out:
+        out["paper_context"]["this_gpu_vs_oracle"] = out["value"] / out["cpu_baseline"]["value"]
+    log("done")
     print(json.dumps(out), flush=True)
 
 

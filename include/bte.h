@@ -109,12 +109,22 @@ typedef struct {
 /* Per-band material data (host arrays of length bands->n): group speed vg [m/s],
  * relaxation time tau [s], density of states per polarisation dos [s/m^3] and
  * polarisation degeneracy deg.  The equilibrium intensity per steradian is
- * I0_b(T) = C_b / (exp(hbar omega_b / k_B T) - 1), C_b = deg hbar omega dos domega / (4 pi). */
+ * I0_b(T) = C_b / (exp(hbar omega_b / k_B T) - 1), C_b = deg hbar omega dos domega / (4 pi).
+ *
+ * Relaxation times may depend on temperature (Sec. 2.2: I0 and tau both do):
+ * tau_b(T) = tau[b] (tau_T0 / T)^tau_exp[b], a scattering rate that grows as
+ * T^tau_exp[b].  Every relaxation term then takes tau at its cell's current
+ * temperature, and the relaxation-time-weighted temperature solves
+ * sum_b (W I0_b(T) - sum_d w_d I_{d,b}) / tau_b(T) = 0 (the relaxation term
+ * conserves energy).  tau_exp NULL (or all zero) keeps tau constant; tau_T0
+ * <= 0 means 300 K.  Batches take constant relaxation times only. */
 typedef struct {
   const double* vg;
   const double* tau;
   const double* dos;
   const double* deg;
+  const double* tau_exp;  /* nullable */
+  double tau_T0;          /* [K] */
 } bte_dispersion;
 
 typedef struct {

@@ -25,6 +25,15 @@
  *     I0_b(T_wall) (isothermal) or the cell's own intensity in the mirrored
  *     direction (specular / symmetry; identical on axis-aligned walls).
  */
+/*
+ *   - Relaxation times that depend on temperature (Sec. 2.2: I0 and tau both
+ *     depend on T; the paper gives no law): tau_b(T) = tau_b (T0 / T)^p_b per
+ *     band entry, i.e. a scattering rate growing as T^p_b.  The sweep takes
+ *     tau at the cell's current temperature; the relaxation-time-weighted
+ *     temperature then solves H(T) = sum_b (W I0_b(T) - e_b) / tau_b(T) = 0
+ *     with e_b = sum_d w_d I_{d,b}, the condition for the relaxation term to
+ *     conserve energy.  All p_b = 0 is the constant-tau path, bit for bit.
+ */
 #include "bte_oracle.h"
 
 #include <math.h>
@@ -52,6 +61,8 @@ struct oracle_bte {
   double* wall_I0[6]; /* [face][b] equilibrium intensity of an isothermal wall */
   double *s, *w, W;
   double *omega, *vg, *tau, *C;
+  double *tau_p, tau_T0; /* tau_b(T) = tau_b (T0 / T)^p_b */
+  int tauT;              /* some p_b != 0 */
   double dt, tol;
   int max_inner, scheme, tdef;
   int* mirror[3]; /* [d] -> mirrored direction across each axis, -1 if none */
@@ -86,6 +97,55 @@ static double equilibrium_dT(const oracle_bte* o, int b, double T) {
 
 static double band_weight(const oracle_bte* o, int b) {
   return o->tdef == ORACLE_T_TAU_WEIGHTED ? 1.0 / o->tau[b] : 1.0;
+}
+
+/* Relaxation time of band b at temperature T. */
+static double tau_at(const oracle_bte* o, int b, double T) {
+  return o->tau[b] * pow(o->tau_T0 / T, o->tau_p[b]);
+}
+
+/* Temperature from per-band direction sums e_b when the weights 1/tau_b(T)
+ * depend on T.  The root of sum_b (W I0_b(T) - e_b) / tau_b(T) = 0 is the
+ * root of K(T) = N(T) / D(T) - 1 with N = W sum_b I0_b(T) / tau_b(T) and
+ * D = sum_b e_b / tau_b(T) (D > 0); Newton runs on K, whose ratio form keeps
+ * the steps in check far from the root (for one band K = W I0(T) / e - 1,
+ * whatever the law), and which for constant tau takes the steps of the
+ * constant-tau inversion.  d/dT (1/tau_b(T)) = p_b / (T tau_b(T)).  Same
+ * accept-first test and stopping rule as the constant-tau inversion. */
+int oracle_invert_temperature_bands(const oracle_bte* o, const double* e, double T_start,
+                                    double* T_out, int* iters) {
+  *iters = 0;
+  *T_out = T_start;
+  if (!(T_start > 0.0)) return ORACLE_E_NUMERIC;
+  double T = T_start;
+  for (int it = 0;; ++it) {
+    double N = 0.0, dN = 0.0, D = 0.0, dD = 0.0;
+    for (int b = 0; b < o->nb; ++b) {
+      double r = 1.0 / tau_at(o, b, T);
+      double dr = o->tau_p[b] / T * r;
+      double i0 = oracle_equilibrium(o, b, T);
+      N += r * o->W * i0;
+      dN += dr * o->W * i0 + r * o->W * equilibrium_dT(o, b, T);
+      D += r * e[b];
+      dD += dr * e[b];
+    }
+    if (!(D > 0.0) || !isfinite(D)) return ORACLE_E_NUMERIC;
+    double K = N / D - 1.0;
+    if (it == 0 && fabs(K) <= NEWTON_ACCEPT_REL) { /* already consistent: keep T */
+      *T_out = T;
+      return ORACLE_OK;
+    }
+    if (it == NEWTON_MAX_ITERS) return ORACLE_E_NUMERIC;
+    double dK = (dN * D - N * dD) / (D * D);
+    double dT = K / dK;
+    T = T - dT;
+    *iters = it + 1;
+    if (!isfinite(T) || !(T > 0.0)) return ORACLE_E_NUMERIC;
+    if (fabs(dT) <= NEWTON_STEP_REL * T) {
+      *T_out = T;
+      return ORACLE_OK;
+    }
+  }
 }
 
 /* F(T) = W sum_b weight_b I0_b(T) */
@@ -163,9 +223,9 @@ oracle_bte* oracle_create(int dim, const int* n, const double* h, const int* wal
                           const double* const* wall_T, const double* T_init, int nd,
                           const double* s, const double* w, int nb, const double* omega,
                           const double* domega, const double* vg, const double* tau,
-                          const double* dos, const double* deg, double dt, double tol,
-                          int max_inner, int scheme, int t_definition, char* err,
-                          int errlen) {
+                          const double* dos, const double* deg, const double* tau_exp,
+                          double tau_T0, double dt, double tol, int max_inner, int scheme,
+                          int t_definition, char* err, int errlen) {
   if (dim != 2 && dim != 3) { set_err(err, errlen, "dim must be 2 or 3"); return NULL; }
   if (n[0] < 1 || n[1] < 1 || n[2] < 1 || (dim == 2 && n[2] != 1)) {
     set_err(err, errlen, "bad mesh size"); return NULL;
@@ -196,12 +256,14 @@ oracle_bte* oracle_create(int dim, const int* n, const double* h, const int* wal
   o->scheme = scheme;
   o->tdef = t_definition;
   o->failed_cell = -1;
+  o->tau_T0 = tau_T0 > 0.0 ? tau_T0 : 300.0;
 
   o->s = (double*)xcalloc((size_t)3 * nd, sizeof(double));
   o->w = (double*)xcalloc(nd, sizeof(double));
   o->omega = (double*)xcalloc(nb, sizeof(double));
   o->vg = (double*)xcalloc(nb, sizeof(double));
   o->tau = (double*)xcalloc(nb, sizeof(double));
+  o->tau_p = (double*)xcalloc(nb, sizeof(double));
   o->C = (double*)xcalloc(nb, sizeof(double));
   size_t ndof = (size_t)o->nc * nd * nb;
   o->In = (double*)xcalloc(ndof, sizeof(double));
@@ -216,7 +278,7 @@ oracle_bte* oracle_create(int dim, const int* n, const double* h, const int* wal
   o->cell_newton = (int*)xcalloc(o->nc, sizeof(int));
   o->cell_fail = (int*)xcalloc(o->nc, sizeof(int));
   for (int a = 0; a < 3; ++a) o->mirror[a] = (int*)xcalloc(nd, sizeof(int));
-  if (!o->s || !o->w || !o->omega || !o->vg || !o->tau || !o->C || !o->In || !o->Ik ||
+  if (!o->s || !o->w || !o->omega || !o->vg || !o->tau || !o->tau_p || !o->C || !o->In || !o->Ik ||
       !o->Inew || !o->Tn || !o->Tk || !o->Tnew || !o->Tprev || !o->cell_num ||
       !o->cell_den || !o->cell_newton || !o->cell_fail || !o->mirror[0] || !o->mirror[1] ||
       !o->mirror[2]) {
@@ -241,6 +303,13 @@ oracle_bte* oracle_create(int dim, const int* n, const double* h, const int* wal
     o->omega[b] = omega[b];
     o->vg[b] = vg[b];
     o->tau[b] = tau[b];
+    o->tau_p[b] = tau_exp ? tau_exp[b] : 0.0;
+    if (!isfinite(o->tau_p[b])) {
+      set_err(err, errlen, "relaxation-time exponents must be finite");
+      oracle_destroy(o);
+      return NULL;
+    }
+    if (o->tau_p[b] != 0.0) o->tauT = 1;
     o->C[b] = deg[b] * HBAR * omega[b] * dos[b] * domega[b] / (4.0 * PI);
   }
 
@@ -301,7 +370,7 @@ void oracle_destroy(oracle_bte* o) {
   if (!o) return;
   for (int a = 0; a < 6; ++a) free(o->wall_I0[a]);
   for (int a = 0; a < 3; ++a) free(o->mirror[a]);
-  free(o->s); free(o->w); free(o->omega); free(o->vg); free(o->tau); free(o->C);
+  free(o->s); free(o->w); free(o->omega); free(o->vg); free(o->tau); free(o->tau_p); free(o->C);
   free(o->In); free(o->Ik); free(o->Inew);
   free(o->Tn); free(o->Tk); free(o->Tnew); free(o->Tprev);
   free(o->cell_num); free(o->cell_den); free(o->cell_newton); free(o->cell_fail);
@@ -321,12 +390,12 @@ void oracle_destroy(oracle_bte* o) {
  * remain.  Also returns the outflow coefficient sum via *c_out.
  */
 static double balance(const oracle_bte* o, const double* I, int P, int x, int y, int z, int d,
-                      int b, double I0P, double* c_out) {
+                      int b, double I0P, double tauP, double* c_out) {
   const double* sd = o->s + 3 * d;
   int coord[3] = {x, y, z};
   int stride[3] = {1, o->n[0], o->n[0] * o->n[1]};
   double IP = I[idx(o, P, d, b)];
-  double r = (I0P - IP) / o->tau[b];
+  double r = (I0P - IP) / tauP;
   double cout = 0.0;
   for (int f = 0; f < 2 * o->dim; ++f) {
     int axis = f / 2;
@@ -363,32 +432,40 @@ static int sweep_and_temperature(oracle_bte* o) {
 #pragma omp parallel for schedule(static) reduction(+ : nfail)
   for (int P = 0; P < o->nc; ++P) {
     int x = P % nx, y = (P / nx) % ny, z = P / (nx * ny);
-    double* I0P = (double*)malloc(sizeof(double) * o->nb);
-    for (int b = 0; b < o->nb; ++b) I0P[b] = oracle_equilibrium(o, b, o->Tk[P]);
+    double* I0P = (double*)malloc(sizeof(double) * 3 * o->nb);
+    double* tauP = I0P + o->nb; /* relaxation time at the cell's current temperature */
+    double* eP = I0P + 2 * o->nb;
+    for (int b = 0; b < o->nb; ++b) {
+      I0P[b] = oracle_equilibrium(o, b, o->Tk[P]);
+      tauP[b] = tau_at(o, b, o->Tk[P]);
+    }
     for (int d = 0; d < o->nd; ++d) {
       for (int b = 0; b < o->nb; ++b) {
         size_t i = idx(o, P, d, b);
         double cout;
-        double r = balance(o, o->Ik, P, x, y, z, d, b, I0P[b], &cout);
+        double r = balance(o, o->Ik, P, x, y, z, d, b, I0P[b], tauP[b], &cout);
         if (o->scheme == ORACLE_EXPLICIT) {
           o->Inew[i] = o->In[i] + o->dt * r;
         } else {
           r += (o->In[i] - o->Ik[i]) / o->dt;
-          double a = 1.0 / o->dt + 1.0 / o->tau[b] + cout;
+          double a = 1.0 / o->dt + 1.0 / tauP[b] + cout;
           o->Inew[i] = o->Ik[i] + r / a;
         }
       }
     }
-    free(I0P);
     /* energy sums: band outer, direction inner */
     double G = 0.0;
     for (int b = 0; b < o->nb; ++b) {
       double Sb = 0.0;
       for (int d = 0; d < o->nd; ++d) Sb += o->w[d] * o->Inew[idx(o, P, d, b)];
+      eP[b] = Sb;
       G += band_weight(o, b) * Sb;
     }
     int it = 0;
-    int st = oracle_invert_temperature(o, G, o->Tk[P], &o->Tnew[P], &it);
+    int st = (o->tauT && o->tdef == ORACLE_T_TAU_WEIGHTED)
+                 ? oracle_invert_temperature_bands(o, eP, o->Tk[P], &o->Tnew[P], &it)
+                 : oracle_invert_temperature(o, G, o->Tk[P], &o->Tnew[P], &it);
+    free(I0P);
     o->cell_newton[P] = it;
     o->cell_fail[P] = (st != ORACLE_OK);
     nfail += (st != ORACLE_OK);

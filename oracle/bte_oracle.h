@@ -57,13 +57,15 @@ typedef struct {
 /* Copies every input array.  On failure returns NULL and writes a message into
  * err (if err != NULL).  wall_T is an array of 6 pointers (NULL unless that wall
  * is isothermal).  Band inputs: omega, domega, group speed vg, relaxation time
- * tau, density of states per polarisation dos, degeneracy deg. */
+ * tau (at temperature tau_T0), density of states per polarisation dos,
+ * degeneracy deg, and (nullable: all zero) the exponents tau_exp of
+ * tau_b(T) = tau_b (tau_T0 / T)^tau_exp_b; tau_T0 <= 0 means 300 K. */
 oracle_bte* oracle_create(int dim, const int* n, const double* h, const int* wall,
                           const double* const* wall_T, const double* T_init,
                           int nd, const double* s, const double* w,
                           int nb, const double* omega, const double* domega,
                           const double* vg, const double* tau, const double* dos,
-                          const double* deg,
+                          const double* deg, const double* tau_exp, double tau_T0,
                           double dt, double tol, int max_inner, int scheme,
                           int t_definition, char* err, int errlen);
 void oracle_destroy(oracle_bte* o);
@@ -95,6 +97,11 @@ double oracle_equilibrium(const oracle_bte* o, int b, double T);
  * iteration count. */
 int oracle_invert_temperature(const oracle_bte* o, double G, double T_start,
                               double* T_out, int* iters);
+/* Temperature from per-band direction sums e[b] = sum_d w_d I_{d,b} with
+ * temperature-dependent relaxation times: Newton on
+ * sum_b (W I0_b(T) - e_b) / tau_b(T) = 0 from T_start. */
+int oracle_invert_temperature_bands(const oracle_bte* o, const double* e, double T_start,
+                                    double* T_out, int* iters);
 /* Mirror map across the given axis (0, 1, 2); -1 entries when not closed. */
 void oracle_mirror_map(const oracle_bte* o, int axis, int* map);
 

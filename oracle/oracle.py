@@ -59,8 +59,9 @@ def _load():
     lib = C.CDLL(_LIB)
     lib.oracle_create.restype = C.c_void_p
     lib.oracle_create.argtypes = [C.c_int, _ip, _dp, _ip, C.POINTER(_dp), _dp, C.c_int, _dp, _dp,
-                                  C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
-                                  C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_int]
+                                  C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
+                                  C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_char_p,
+                                  C.c_int]
     lib.oracle_destroy.argtypes = [C.c_void_p]
     lib.oracle_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(_Stats)]
     lib.oracle_step_warm.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int, C.POINTER(_Stats)]
@@ -74,6 +75,7 @@ def _load():
     lib.oracle_equilibrium.restype = C.c_double
     lib.oracle_equilibrium.argtypes = [C.c_void_p, C.c_int, C.c_double]
     lib.oracle_invert_temperature.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp, _ip]
+    lib.oracle_invert_temperature_bands.argtypes = [C.c_void_p, _dp, C.c_double, _dp, _ip]
     lib.oracle_mirror_map.argtypes = [C.c_void_p, C.c_int, _ip]
     _lib = lib
     return lib
@@ -116,11 +118,14 @@ class Oracle:
         for i in range(6):
             a = inst.wall_T[i]
             wt[i] = _ptr(f64(a)) if a is not None else _dp()
+        tau_exp = getattr(inst, "tau_exp", None)
+        tau_T0 = getattr(inst, "tau_T0", 300.0)
         err = C.create_string_buffer(256)
         self._h = lib.oracle_create(
             int(inst.dim), n, h, wall, wt, _ptr(f64(inst.T_init)), self.nd, _ptr(f64(inst.s)),
             _ptr(f64(inst.w)), self.nb, _ptr(f64(inst.omega)), _ptr(f64(inst.domega)),
             _ptr(f64(inst.vg)), _ptr(f64(inst.tau)), _ptr(f64(inst.dos)), _ptr(f64(inst.deg)),
+            _ptr(f64(tau_exp)) if tau_exp is not None else _dp(), float(tau_T0),
             float(inst.dt if dt is None else dt), float(inst.tol if tol is None else tol),
             int(inst.max_inner if max_inner is None else max_inner),
             int(inst.scheme if scheme is None else scheme),
@@ -196,6 +201,18 @@ class Oracle:
         it = C.c_int(0)
         rc = self.lib.oracle_invert_temperature(self._h, float(G), float(T_start), C.byref(T),
                                                 C.byref(it))
+        if rc != 0:
+            raise OracleError("Newton inversion failed")
+        return T.value, it.value
+
+    def invert_temperature_bands(self, e, T_start: float):
+        """Temperature from per-band direction sums e_b with temperature-
+        dependent relaxation times."""
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        T = C.c_double(0.0)
+        it = C.c_int(0)
+        rc = self.lib.oracle_invert_temperature_bands(self._h, _ptr(e), float(T_start),
+                                                      C.byref(T), C.byref(it))
         if rc != 0:
             raise OracleError("Newton inversion failed")
         return T.value, it.value

@@ -32,7 +32,8 @@ BTE_WARM_NONE, BTE_WARM_T, BTE_WARM_T_SHIFT = 0, 1, 2
 
 # every symbol include/bte.h declares
 EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "bte_intensity",
-           "bte_energy", "bte_set_state", "bte_sweep_time", "bte_sweep_layout",
+           "bte_energy", "bte_set_fields", "bte_state_size", "bte_get_state", "bte_set_state",
+           "bte_sweep_time", "bte_sweep_layout",
            "bte_nn_param_count", "bte_nn_params",
            "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_autotune",
            "bte_batch_create", "bte_batch_step", "bte_batch_destroy", "bte_destroy",
@@ -56,7 +57,8 @@ class bte_bands(C.Structure):
 
 
 class bte_dispersion(C.Structure):
-    _fields_ = [("vg", _dp), ("tau", _dp), ("dos", _dp), ("deg", _dp)]
+    _fields_ = [("vg", _dp), ("tau", _dp), ("dos", _dp), ("deg", _dp), ("tau_exp", _dp),
+                ("tau_T0", C.c_double)]
 
 
 class bte_options(C.Structure):
@@ -72,6 +74,17 @@ class bte_step_stats(C.Structure):
     _fields_ = [("inner", C.c_int), ("converged", C.c_int), ("newton_max", C.c_int),
                 ("warm", C.c_int), ("res", C.c_double), ("fallbacks", C.c_int),
                 ("trained", C.c_int), ("nn_loss", C.c_double)]
+
+
+class bte_state_header(C.Structure):
+    _fields_ = [("magic", C.c_char * 8), ("version", C.c_int), ("header_bytes", C.c_int),
+                ("dim", C.c_int), ("n", C.c_int * 3), ("nd", C.c_int), ("nb", C.c_int),
+                ("precision", C.c_int), ("scheme", C.c_int), ("warm_start", C.c_int),
+                ("nn_rec", C.c_int), ("layout", C.c_int * 4), ("steps", C.c_longlong),
+                ("nn_recorded", C.c_int), ("nn_trained", C.c_int), ("nn_off", C.c_int),
+                ("nn_warm_steps", C.c_int), ("nn_warm_sweeps", C.c_int), ("nn_adam_t", C.c_int),
+                ("nn_last_batch", C.c_int), ("nn_params", C.c_int),
+                ("off", C.c_ulonglong * 11), ("total", C.c_ulonglong)]
 
 
 class BteError(RuntimeError):
@@ -106,7 +119,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.bte_temperature.argtypes = [C.c_void_p, _dp, C.c_size_t]
     lib.bte_intensity.argtypes = [C.c_void_p, _dp, C.c_size_t]
     lib.bte_energy.argtypes = [C.c_void_p, _dp, C.c_size_t]
-    lib.bte_set_state.argtypes = [C.c_void_p, _dp, C.c_size_t, _dp, C.c_size_t]
+    lib.bte_set_fields.argtypes = [C.c_void_p, _dp, C.c_size_t, _dp, C.c_size_t]
+    lib.bte_state_size.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    lib.bte_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.bte_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     lib.bte_sweep_time.argtypes = [C.c_void_p, _dp, _ip]
     lib.bte_sweep_layout.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip]
     _fp = C.POINTER(C.c_float)
@@ -160,7 +176,10 @@ class _Inputs:
         m.T_init = ptr(inst.T_init)
         d = bte_dirs(int(inst.s.shape[0]), ptr(inst.s), ptr(inst.w))
         b = bte_bands(int(inst.omega.shape[0]), ptr(inst.omega), ptr(inst.domega))
-        disp = bte_dispersion(ptr(inst.vg), ptr(inst.tau), ptr(inst.dos), ptr(inst.deg))
+        tau_exp = getattr(inst, "tau_exp", None)
+        disp = bte_dispersion(ptr(inst.vg), ptr(inst.tau), ptr(inst.dos), ptr(inst.deg),
+                              ptr(tau_exp) if tau_exp is not None else _dp(),
+                              float(getattr(inst, "tau_T0", 300.0)))
         o = bte_options()
         o.dt = float(opts["dt"])
         o.tol = float(opts["tol"])
@@ -217,7 +236,9 @@ class Solver:
         self.workspace = torch.empty(self._ws_bytes, dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:
             raise BteError(BTE_E_INVAL, "torch workspace is not 256-byte aligned")
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own unless one is given: the library captures inner
+        # iterations as graphs, which the null stream cannot hold
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         inp.opt.stream = C.c_void_p(int(self.stream.cuda_stream))
         inp.opt.workspace = C.c_void_p(self.workspace.data_ptr())
         inp.opt.workspace_bytes = int(nbytes.value)
@@ -257,11 +278,28 @@ class Solver:
         _check(self.lib.bte_intensity(self._ctx, I.ctypes.data_as(_dp), I.size))
         return I.reshape(self.nb, self.nd, self.nc)
 
-    def set_state(self, I: np.ndarray, T: np.ndarray):
+    def set_fields(self, I: np.ndarray, T: np.ndarray):
+        """Replaces the intensity [N_b, N_d, N_c] and temperature [N_c] of the
+        current time level (T_{n-1} is set to T; E is recomputed)."""
         I = _f64(I).reshape(-1)
         T = _f64(T).reshape(-1)
-        _check(self.lib.bte_set_state(self._ctx, I.ctypes.data_as(_dp), I.size,
-                                      T.ctypes.data_as(_dp), T.size))
+        _check(self.lib.bte_set_fields(self._ctx, I.ctypes.data_as(_dp), I.size,
+                                       T.ctypes.data_as(_dp), T.size))
+
+    def get_state(self) -> bytearray:
+        """Checkpoint of everything the next steps depend on (bte_get_state)."""
+        n = C.c_size_t(0)
+        _check(self.lib.bte_state_size(self._ctx, C.byref(n)))
+        buf = bytearray(n.value)
+        cbuf = (C.c_char * len(buf)).from_buffer(buf)
+        _check(self.lib.bte_get_state(self._ctx, C.cast(cbuf, C.c_void_p), len(buf)))
+        return buf
+
+    def set_state(self, state) -> None:
+        """Restores a checkpoint taken by get_state (bte_set_state)."""
+        buf = bytearray(state)
+        cbuf = (C.c_char * len(buf)).from_buffer(buf)
+        _check(self.lib.bte_set_state(self._ctx, C.cast(cbuf, C.c_void_p), len(buf)))
 
     # ---- learned warm start
     def nn_param_count(self) -> int:
@@ -342,6 +380,38 @@ class Solver:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def parse_state(buf) -> dict:
+    """Splits a state written by bte_get_state into its header fields and
+    numpy views of its sections (layout as documented in include/bte.h)."""
+    h = bte_state_header.from_buffer_copy(bytes(buf[:C.sizeof(bte_state_header)]))
+    nc = h.n[0] * h.n[1] * h.n[2]
+    out = {name: getattr(h, name) for name, _ in bte_state_header._fields_
+           if name not in ("magic", "n", "layout", "off")}
+    out["n"] = list(h.n)
+    out["layout"] = list(h.layout)
+    mv = memoryview(bytes(buf))
+
+    def sec(i, dtype, shape):
+        if h.off[i] == 0:
+            return None
+        cnt = int(np.prod(shape))
+        return np.frombuffer(mv, dtype=dtype, count=cnt, offset=h.off[i]).reshape(shape)
+
+    real = np.float64 if h.precision == BTE_FP64 else np.float32
+    out["I"] = sec(0, real, (h.nb, h.nd, nc))
+    out["T"] = sec(1, np.float64, (nc,))
+    out["T_prev"] = sec(2, np.float64, (nc,))
+    out["E"] = sec(3, np.float64, (nc,))
+    out["I0"] = sec(4, np.float64, (h.nb, nc))
+    out["Iref"] = sec(5, np.float64, (h.nb,))
+    out["plain_sweeps"] = sec(6, np.int32, (h.nn_rec,))
+    out["params"] = sec(7, np.float32, (h.nn_params,))
+    out["adam_m"] = sec(8, np.float32, (h.nn_params,))
+    out["adam_v"] = sec(9, np.float32, (h.nn_params,))
+    out["history"] = sec(10, np.float32, (h.nn_rec, 4, nc))
+    return out
 
 
 def _stats_dict(s) -> dict:

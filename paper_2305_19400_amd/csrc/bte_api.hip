@@ -38,6 +38,8 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr int kRing = 4;         // pinned control snapshots in flight
+constexpr int kDeferSteps = 64;  // steps queued before the host reads their control words
+constexpr int kMaxStepGraphs = 24;
 constexpr double kMirrorTol = 1e-12;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -45,7 +47,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t ctl, coef, dflags, mirror, w, Cb, xfac, inv_tau, fweight, Iref;
   size_t wallT[6], wallI0[6], wallS[6];
-  size_t T, Tprev, E, I0, S, part;
+  size_t T, Tprev, E, I0, S, part, relax, tau_p;
   // learned warm start (present if warm_start != 0)
   size_t nn_params, nn_grad, nn_m, nn_v, nn_W1b, nn_W2b, nn_W2Tb, nn_y, nn_hist, nn_loss,
       nn_fallbacks, nn_XT, nn_H1T, nn_dZ1T, nn_dZ2T, nn_part, nn_shift, nn_guess;
@@ -108,6 +110,10 @@ Layout make_layout(const Shape& s) {
   L.I0 = take(sizeof(double) * (size_t)s.nb * s.ncp);
   L.S = take(sizeof(double) * (size_t)s.ndg_cap * s.nb * s.ncp);
   L.part = take(sizeof(double) * 2 * (size_t)s.nparts_cap);
+  // scattering rates at the cells' temperatures, used if the relaxation
+  // times depend on temperature (the dispersion is not known when sizing)
+  L.relax = take(sizeof(double) * (size_t)s.nb * s.ncp);
+  L.tau_p = take(sizeof(double) * (size_t)s.nb);
   if (s.warm) {
     const NnLayout N = make_nn_layout(s.dim);
     const size_t P = (size_t)N.total;
@@ -278,6 +284,20 @@ struct bte_ctx {
   Control* ctl;
   Control* host_ring;  // pinned
   hipEvent_t ring_ev[kRing];
+  Control* host_steps;  // pinned, one per step queued without a host wait
+  // captured chunks of inner iterations of free-running steps, one per
+  // arrangement of the three intensity fields (see enqueue_chunk)
+  struct StepGraph {
+    const void* In;
+    const void* Ia;
+    const void* Ib;
+    const double* shift;
+    int first;
+    SweepPlan plan;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<StepGraph> step_graphs;
   std::vector<hipEvent_t> t_start, t_stop;
   double timing_ms;
   int timing_count;
@@ -309,6 +329,7 @@ struct bte_ctx {
   std::vector<bte_ctx*>* train_queue = nullptr;
   bool nn_loss_pending = false;     // trained; loss not read yet
   int nn_last_batch = 1;            // samples of the last minibatch
+  long long steps_taken = 0;        // time steps completed since create
   bool poisoned;
 };
 
@@ -492,7 +513,8 @@ int step_begin(bte_ctx* ctx, int fixed, StepState* ss) {
 // Everything after the inner loop, given the final control words: error
 // report, sweep timing, I^{n+1} <- newest iterate, the network's training
 // target and training, statistics.
-int step_finish(bte_ctx* ctx, const StepState& ss, const Control& fin, bte_step_stats* st) {
+int step_finish(bte_ctx* ctx, const StepState& ss, const Control& fin, bte_step_stats* st,
+                bool swapped = false) {
   const int nc = ctx->s.nc;
   if (fin.err_cell != INT_MAX) {
     const int P = fin.err_cell;
@@ -511,8 +533,11 @@ int step_finish(bte_ctx* ctx, const StepState& ss, const Control& fin, bte_step_
     }
   }
   // the newest iterate becomes I^{n+1}
-  void*& last = ((fin.k - 1) & 1) ? ctx->Ib : ctx->Ia;
-  std::swap(ctx->In, last);
+  if (!swapped) {
+    void*& last = ((fin.k - 1) & 1) ? ctx->Ib : ctx->Ia;
+    std::swap(ctx->In, last);
+  }
+  ctx->steps_taken += 1;
   int trained = 0, fallbacks = 0;
   double loss = 0.0;
   if (ss.warm) {
@@ -563,23 +588,107 @@ int step_finish(bte_ctx* ctx, const StepState& ss, const Control& fin, bte_step_
   return BTE_OK;
 }
 
+// Inner iterations per captured chunk of a free-running step (BTE_GRAPH_CHUNK
+// overrides; 0 turns the graphs off).
+int graph_chunk() {
+  static const int c = env_int("BTE_GRAPH_CHUNK", 4);
+  return c;
+}
+
+void drop_step_graphs(bte_ctx* ctx) {
+  for (auto& g : ctx->step_graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  ctx->step_graphs.clear();
+}
+
+bool same_plan(const SweepPlan& a, const SweepPlan& b) {
+  return a.kind == b.kind && a.ry == b.ry && a.rz == b.rz && a.ndg == b.ndg &&
+         a.ntiles == b.ntiles && a.nparts == b.nparts;
+}
+
+// Enqueues iterations [j0, j0 + chunk) of a free-running step as one graph
+// launch.  Which field an iteration reads and writes depends only on whether it
+// is the step's first (it reads I^n) and on its parity, so with an even chunk
+// every chunk after the first replays the same launches; the graphs are kept
+// per arrangement of the three fields (the field that holds I^n changes from
+// step to step), built on first use.  Surplus iterations after convergence
+// return at once (device flag).
+int enqueue_chunk(bte_ctx* ctx, int j0, int chunk) {
+  const int first = j0 == 0;
+  const double* shift = first ? ctx->first_shift : nullptr;
+  ctx->first_shift = first ? ctx->first_shift : nullptr;
+  for (const auto& g : ctx->step_graphs)
+    if (g.In == ctx->In && g.Ia == ctx->Ia && g.Ib == ctx->Ib && g.shift == shift &&
+        g.first == first && same_plan(g.plan, ctx->s.plan)) {
+      HIP_TRY(hipGraphLaunch(g.exec, ctx->stream));
+      return BTE_OK;
+    }
+  if ((int)ctx->step_graphs.size() >= kMaxStepGraphs) drop_step_graphs(ctx);
+  bte_ctx::StepGraph g{ctx->In, ctx->Ia, ctx->Ib, shift, first, ctx->s.plan, nullptr, nullptr};
+  HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  int rc = BTE_OK;
+  const double* saved = ctx->first_shift;
+  for (int jj = 0; jj < chunk && rc == BTE_OK; ++jj) {
+    // iteration j0 + jj, with j0 = 0 or any even j0 >= 2
+    const int j = first ? jj : 2 + jj;
+    ctx->first_shift = shift;
+    rc = enqueue_iteration(ctx, j, 0);
+  }
+  ctx->first_shift = saved;
+  hipGraph_t graph = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(ctx->stream, &graph);
+  if (rc != BTE_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  HIP_TRY(e_end);
+  g.graph = graph;
+  const hipError_t e_inst = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  if (e_inst != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e_inst);
+  }
+  ctx->step_graphs.push_back(g);
+  HIP_TRY(hipGraphLaunch(g.exec, ctx->stream));
+  return BTE_OK;
+}
+
 int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
   StepState ss;
   int rc = step_begin(ctx, fixed, &ss);
   if (rc != BTE_OK) return rc;
   HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
-  for (int j = 0; j < ss.limit; ++j) {
-    rc = enqueue_iteration(ctx, j, ss.check ? 0 : fixed);
-    if (rc != BTE_OK) return rc;
-    if (ss.check) {
-      // Keep one iteration queued ahead of the convergence test so the device
-      // never waits for the host; a surplus iteration is a no-op on the device.
-      HIP_TRY(hipMemcpyAsync(&ctx->host_ring[j % kRing], ctx->ctl, sizeof(Control),
+  const int chunk = graph_chunk() & ~1;
+  if (ss.check && chunk > 0 && !ctx->opt.timing && ctx->stream != nullptr) {
+    // Free-running: captured chunks of iterations, one chunk queued ahead of
+    // the convergence test.
+    for (int m = 0; m * chunk < ss.limit; ++m) {
+      rc = enqueue_chunk(ctx, m * chunk, chunk);
+      if (rc != BTE_OK) return rc;
+      HIP_TRY(hipMemcpyAsync(&ctx->host_ring[m % kRing], ctx->ctl, sizeof(Control),
                              hipMemcpyDeviceToHost, ctx->stream));
-      HIP_TRY(hipEventRecord(ctx->ring_ev[j % kRing], ctx->stream));
-      if (j >= 1) {
-        HIP_TRY(hipEventSynchronize(ctx->ring_ev[(j - 1) % kRing]));
-        if (ctx->host_ring[(j - 1) % kRing].converged) break;
+      HIP_TRY(hipEventRecord(ctx->ring_ev[m % kRing], ctx->stream));
+      if (m >= 1) {
+        HIP_TRY(hipEventSynchronize(ctx->ring_ev[(m - 1) % kRing]));
+        if (ctx->host_ring[(m - 1) % kRing].converged) break;
+      }
+    }
+  } else {
+    for (int j = 0; j < ss.limit; ++j) {
+      rc = enqueue_iteration(ctx, j, ss.check ? 0 : fixed);
+      if (rc != BTE_OK) return rc;
+      if (ss.check) {
+        // Keep one iteration queued ahead of the convergence test so the device
+        // never waits for the host; a surplus iteration is a no-op on the device.
+        HIP_TRY(hipMemcpyAsync(&ctx->host_ring[j % kRing], ctx->ctl, sizeof(Control),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipEventRecord(ctx->ring_ev[j % kRing], ctx->stream));
+        if (j >= 1) {
+          HIP_TRY(hipEventSynchronize(ctx->ring_ev[(j - 1) % kRing]));
+          if (ctx->host_ring[(j - 1) % kRing].converged) break;
+        }
       }
     }
   }
@@ -588,6 +697,48 @@ int one_step(bte_ctx* ctx, int fixed, bte_step_stats* st) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   const Control fin = ctx->host_ring[0];
   return step_finish(ctx, ss, fin, st);
+}
+
+// Steps whose sweep count the host knows beforehand (forward Euler: one; a
+// replayed schedule: the given count) are queued back to back: the field
+// swap at the end of each is known, so the host reads their control words
+// only every kDeferSteps steps.  Contexts with a learned warm start step one
+// at a time (the guess, the recording and the guard read device results).
+bool steps_known(const bte_ctx* ctx, const int* fixed_inner, int nsteps) {
+  if (ctx->s.warm || ctx->opt.timing) return false;
+  if (ctx->opt.scheme == BTE_EXPLICIT_EULER) return true;
+  if (!fixed_inner) return false;
+  for (int i = 0; i < nsteps; ++i)
+    if (fixed_inner[i] <= 0) return false;
+  return true;
+}
+
+int run_known_steps(bte_ctx* ctx, int nsteps, const int* fixed_inner, bte_step_stats* stats) {
+  StepState ss[kDeferSteps];
+  for (int i0 = 0; i0 < nsteps; i0 += kDeferSteps) {
+    const int n = std::min(kDeferSteps, nsteps - i0);
+    for (int q = 0; q < n; ++q) {
+      const int fixed = fixed_inner ? fixed_inner[i0 + q] : 0;
+      int rc = step_begin(ctx, fixed, &ss[q]);
+      if (rc != BTE_OK) return rc;
+      HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
+      for (int j = 0; j < ss[q].limit; ++j) {
+        rc = enqueue_iteration(ctx, j, fixed);
+        if (rc != BTE_OK) return rc;
+      }
+      HIP_TRY(hipMemcpyAsync(&ctx->host_steps[q], ctx->ctl, sizeof(Control),
+                             hipMemcpyDeviceToHost, ctx->stream));
+      void*& last = ((ss[q].limit - 1) & 1) ? ctx->Ib : ctx->Ia;
+      std::swap(ctx->In, last);
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < n; ++q) {
+      const int rc = step_finish(ctx, ss[q], ctx->host_steps[q],
+                                 stats ? &stats[i0 + q] : nullptr, true);
+      if (rc != BTE_OK) return rc;
+    }
+  }
+  return BTE_OK;
 }
 
 }  // namespace
@@ -623,13 +774,21 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
 
   // ---- host-side tables
   const int nd = s.nd, nb = s.nb;
+  bool tauT = false;
   for (int b = 0; b < nb; ++b) {
     const double vals[6] = {bands->omega[b], bands->domega[b], disp->vg[b], disp->tau[b],
                             disp->dos[b], disp->deg[b]};
     for (double v : vals)
       if (!(v > 0.0) || !std::isfinite(v))
         return fail(BTE_E_INVAL, "band %d: omega, domega, vg, tau, dos, deg must be positive", b);
+    if (disp->tau_exp) {
+      if (!std::isfinite(disp->tau_exp[b]))
+        return fail(BTE_E_INVAL, "band %d: relaxation-time exponent must be finite", b);
+      tauT |= disp->tau_exp[b] != 0.0;
+    }
   }
+  if (tauT && !(disp->tau_T0 <= 0.0 || std::isfinite(disp->tau_T0)))
+    return fail(BTE_E_INVAL, "tau_T0 must be finite");
   for (int i = 0; i < nd; ++i)
     if (!(dirs->w[i] > 0.0) || !std::isfinite(dirs->w[i]))
       return fail(BTE_E_INVAL, "direction %d has a non-positive weight", i);
@@ -667,6 +826,10 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
     }
     dflags[i] = fl;
   }
+  // Forward Euler keeps every intensity a convex combination of old values
+  // (positive, bounded) only if dt (1/tau_b + sum_a c_a) <= 1 everywhere.
+  double max_rate = 0.0;
+  int worst_b = 0, worst_d = 0;
   for (int b = 0; b < nb; ++b) {
     Cb[b] = disp->deg[b] * kHbar * bands->omega[b] * disp->dos[b] * bands->domega[b] / (4.0 * kPi);
     xfac[b] = kHbar * bands->omega[b] / kBoltzmann;
@@ -680,8 +843,19 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
         diag += cf.c[a];
       }
       cf.scale = opt->scheme == BTE_EXPLICIT_EULER ? opt->dt : 1.0 / diag;
+      const double rate = inv_tau[b] + cf.c[0] + cf.c[1] + cf.c[2];
+      if (rate > max_rate) {
+        max_rate = rate;
+        worst_b = b;
+        worst_d = i;
+      }
     }
   }
+  if (opt->scheme == BTE_EXPLICIT_EULER && opt->dt * max_rate > 1.0 + 1e-12)
+    return fail(BTE_E_INVAL,
+                "explicit step too large: dt (1/tau + sum v|s_a|/h_a) = %.6g > 1 for band %d, "
+                "direction %d (largest stable dt %.6g s)",
+                opt->dt * max_rate, worst_b, worst_d, 1.0 / max_rate);
 
   ctx = new (std::nothrow) bte_ctx();
   if (!ctx) return fail(BTE_E_NOMEM, "out of host memory");
@@ -693,6 +867,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   ctx->ws = static_cast<char*>(opt->workspace);
   ctx->poisoned = false;
   ctx->host_ring = nullptr;
+  ctx->host_steps = nullptr;
   for (auto& e : ctx->ring_ev) e = nullptr;
   char* ws = ctx->ws;
   ctx->ctl = at<Control>(ws, L.ctl);
@@ -759,6 +934,11 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   t.inv_tau = at<double>(ws, L.inv_tau);
   t.fweight = at<double>(ws, L.fweight);
   t.Iref = at<double>(ws, L.Iref);
+  t.tau_p = at<double>(ws, L.tau_p);
+  t.relax = tauT ? at<double>(ws, L.relax) : nullptr;
+  t.tau_T0 = disp->tau_T0 > 0.0 ? disp->tau_T0 : 300.0;
+  t.tau_weighted = opt->t_definition == BTE_T_TAU_WEIGHTED;
+  t.explicit_scheme = opt->scheme == BTE_EXPLICIT_EULER;
   t.W = W;
   for (int f = 0; f < 6; ++f) {
     t.wall[f] = (f < 2 * s.dim) ? mesh->wall[f] : BTE_WALL_SPECULAR;
@@ -783,6 +963,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
     }                                                                                  \
   } while (0)
   CREATE_TRY(hipHostMalloc((void**)&ctx->host_ring, sizeof(Control) * kRing));
+  CREATE_TRY(hipHostMalloc((void**)&ctx->host_steps, sizeof(Control) * kDeferSteps));
   for (auto& e : ctx->ring_ev) CREATE_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   CREATE_TRY(up(L.coef, coef.data(), sizeof(Coef) * coef.size()));
   CREATE_TRY(up(L.dflags, dflags.data(), sizeof(int) * dflags.size()));
@@ -792,6 +973,12 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   CREATE_TRY(up(L.xfac, xfac.data(), sizeof(double) * nb));
   CREATE_TRY(up(L.inv_tau, inv_tau.data(), sizeof(double) * nb));
   CREATE_TRY(up(L.fweight, fweight.data(), sizeof(double) * nb));
+  {
+    std::vector<double> tau_p(nb, 0.0);
+    if (disp->tau_exp) tau_p.assign(disp->tau_exp, disp->tau_exp + nb);
+    CREATE_TRY(up(L.tau_p, tau_p.data(), sizeof(double) * nb));
+    CREATE_TRY(hipStreamSynchronize(ctx->stream));  // the vector goes out of scope
+  }
   CREATE_TRY(up(L.T, mesh->T_init, sizeof(double) * s.nc));
   for (int f = 0; f < 6; ++f) {
     if (!s.iso[f]) continue;
@@ -849,6 +1036,7 @@ int bte_step(bte_ctx* ctx, int nsteps, const int* fixed_inner, bte_step_stats* s
   if (!ctx) return fail(BTE_E_INVAL, "null context");
   if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned by an earlier device error");
   if (nsteps < 0) return fail(BTE_E_INVAL, "nsteps must be >= 0");
+  if (steps_known(ctx, fixed_inner, nsteps)) return run_known_steps(ctx, nsteps, fixed_inner, stats);
   for (int i = 0; i < nsteps; ++i) {
     const int fixed = fixed_inner ? fixed_inner[i] : 0;
     int rc = one_step(ctx, fixed, stats ? &stats[i] : nullptr);
@@ -910,7 +1098,7 @@ int bte_intensity(bte_ctx* ctx, double* I_out, size_t n) {
   return BTE_OK;
 }
 
-int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size_t n_cells) {
+int bte_set_fields(bte_ctx* ctx, const double* I, size_t n, const double* T, size_t n_cells) {
   if (!ctx) return fail(BTE_E_INVAL, "null context");
   if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
   if (!I || !T) return fail(BTE_E_INVAL, "null state");
@@ -942,9 +1130,215 @@ int bte_set_state(bte_ctx* ctx, const double* I, size_t n, const double* T, size
   HIP_TRY(hipMemcpyAsync(ctx->Tprev, T, sizeof(double) * n_cells, hipMemcpyHostToDevice,
                          ctx->stream));
   HIP_TRY(launch_equilibrium(ctx->stream, ctx->g, ctx->t, ctx->T, ctx->I0, nullptr));
+  // the energy density of the new intensity (the warm start's next input)
+  if (ctx->opt.precision == BTE_FP64)
+    HIP_TRY(launch_energy<double>(ctx->stream, ctx->g, ctx->t, static_cast<double*>(ctx->In),
+                                  ctx->E));
+  else
+    HIP_TRY(launch_energy<float>(ctx->stream, ctx->g, ctx->t, static_cast<float*>(ctx->In),
+                                 ctx->E));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return BTE_OK;
 }
+
+// ---------------------------------------------------------------- checkpoint
+namespace {
+
+enum StateSection {
+  kSecI = 0, kSecT, kSecTprev, kSecE, kSecI0, kSecIref, kSecPlain, kSecParams, kSecM, kSecV,
+  kSecHist, kStateSections
+};
+static_assert(kStateSections == 11, "bte_state_header.off has 11 sections");
+constexpr char kStateMagic[8] = {'B', 'T', 'E', 'S', 'T', 'A', 'T', '1'};
+
+// Header (shape, counters) and section offsets of this context's state.
+bte_state_header state_header(const bte_ctx* ctx) {
+  bte_state_header h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, kStateMagic, 8);
+  h.version = 1;
+  h.header_bytes = (int)sizeof(bte_state_header);
+  const Shape& s = ctx->s;
+  h.dim = s.dim;
+  h.n[0] = s.nx;
+  h.n[1] = s.ny;
+  h.n[2] = s.nz;
+  h.nd = s.nd;
+  h.nb = s.nb;
+  h.precision = ctx->opt.precision;
+  h.scheme = ctx->opt.scheme;
+  h.warm_start = s.warm;
+  h.nn_rec = s.warm ? s.nn_rec : 0;
+  h.layout[0] = s.plan.kind;
+  h.layout[1] = s.plan.ry;
+  h.layout[2] = s.plan.rz;
+  h.layout[3] = s.plan.ndg;
+  h.steps = ctx->steps_taken;
+  h.nn_recorded = ctx->nn_nrec;
+  h.nn_trained = ctx->nn_ready;
+  h.nn_off = ctx->nn_off;
+  h.nn_warm_steps = ctx->nn_warm_steps;
+  h.nn_warm_sweeps = ctx->nn_warm_sweeps;
+  h.nn_adam_t = ctx->nn_adam_t;
+  h.nn_last_batch = ctx->nn_last_batch;
+  h.nn_params = s.warm ? ctx->nnL.total : 0;
+  const size_t nc = s.nc;
+  size_t off = align_up(sizeof(bte_state_header));
+  auto take = [&](int sec, size_t bytes) {
+    h.off[sec] = off;
+    off = align_up(off + bytes);
+  };
+  take(kSecI, s.real_size * (size_t)s.nb * s.nd * nc);
+  take(kSecT, sizeof(double) * nc);
+  take(kSecTprev, sizeof(double) * nc);
+  take(kSecE, sizeof(double) * nc);
+  take(kSecI0, sizeof(double) * (size_t)s.nb * nc);
+  take(kSecIref, sizeof(double) * (size_t)s.nb);
+  if (s.warm) {
+    const size_t P = (size_t)ctx->nnL.total;
+    take(kSecPlain, sizeof(int) * (size_t)s.nn_rec);
+    take(kSecParams, sizeof(float) * P);
+    take(kSecM, sizeof(float) * P);
+    take(kSecV, sizeof(float) * P);
+    take(kSecHist, sizeof(float) * 4 * (size_t)s.nn_rec * nc);
+  }
+  h.total = off;
+  return h;
+}
+
+}  // namespace
+
+int bte_state_size(bte_ctx* ctx, size_t* bytes) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  if (!bytes) return fail(BTE_E_INVAL, "bytes is null");
+  *bytes = (size_t)state_header(ctx).total;
+  return BTE_OK;
+}
+
+int bte_get_state(bte_ctx* ctx, void* buf, size_t bytes) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
+  if (!buf) return fail(BTE_E_INVAL, "null buffer");
+  const bte_state_header h = state_header(ctx);
+  if (bytes < h.total)
+    return fail(BTE_E_STATE, "state needs %llu bytes, buffer has %zu", h.total, bytes);
+  char* out = static_cast<char*>(buf);
+  memcpy(out, &h, sizeof h);
+  const Shape& s = ctx->s;
+  const size_t nc = s.nc, rows = (size_t)s.nb * s.nd;
+  auto d2h = [&](int sec, const void* src, size_t n) {
+    return hipMemcpyAsync(out + h.off[sec], src, n, hipMemcpyDeviceToHost, ctx->stream);
+  };
+  HIP_TRY(hipMemcpy2DAsync(out + h.off[kSecI], s.real_size * nc, ctx->In, s.real_size * s.ncp,
+                           s.real_size * nc, rows, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(d2h(kSecT, ctx->T, sizeof(double) * nc));
+  HIP_TRY(d2h(kSecTprev, ctx->Tprev, sizeof(double) * nc));
+  HIP_TRY(d2h(kSecE, ctx->E, sizeof(double) * nc));
+  HIP_TRY(hipMemcpy2DAsync(out + h.off[kSecI0], sizeof(double) * nc, ctx->I0,
+                           sizeof(double) * s.ncp, sizeof(double) * nc, (size_t)s.nb,
+                           hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(d2h(kSecIref, ctx->t.Iref, sizeof(double) * s.nb));
+  if (s.warm) {
+    int* plain = reinterpret_cast<int*>(out + h.off[kSecPlain]);
+    for (int i = 0; i < s.nn_rec; ++i)
+      plain[i] = i < (int)ctx->nn_plain_sweeps.size() ? ctx->nn_plain_sweeps[i] : 0;
+    const size_t P = (size_t)ctx->nnL.total;
+    HIP_TRY(d2h(kSecParams, ctx->nnB.params, sizeof(float) * P));
+    HIP_TRY(d2h(kSecM, ctx->nnB.adam_m, sizeof(float) * P));
+    HIP_TRY(d2h(kSecV, ctx->nnB.adam_v, sizeof(float) * P));
+    HIP_TRY(d2h(kSecHist, ctx->nnB.hist, sizeof(float) * 4 * (size_t)s.nn_rec * nc));
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BTE_OK;
+}
+
+int bte_set_state(bte_ctx* ctx, const void* buf, size_t bytes) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
+  if (!buf) return fail(BTE_E_INVAL, "null buffer");
+  if (bytes < sizeof(bte_state_header)) return fail(BTE_E_STATE, "state is truncated");
+  bte_state_header h;
+  memcpy(&h, buf, sizeof h);
+  const bte_state_header mine = state_header(ctx);
+  if (memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1 ||
+      h.header_bytes != (int)sizeof(bte_state_header))
+    return fail(BTE_E_STATE, "not a state written by bte_get_state (version 1)");
+  if (h.dim != mine.dim || h.n[0] != mine.n[0] || h.n[1] != mine.n[1] || h.n[2] != mine.n[2] ||
+      h.nd != mine.nd || h.nb != mine.nb)
+    return fail(BTE_E_STATE, "state of a %dD %dx%dx%d mesh with %d directions and %d band "
+                "entries, context has %dD %dx%dx%d, %d, %d", h.dim, h.n[0], h.n[1], h.n[2], h.nd,
+                h.nb, mine.dim, mine.n[0], mine.n[1], mine.n[2], mine.nd, mine.nb);
+  if (h.precision != mine.precision || h.scheme != mine.scheme ||
+      h.warm_start != mine.warm_start || h.nn_rec != mine.nn_rec ||
+      h.nn_params != mine.nn_params)
+    return fail(BTE_E_STATE, "state has another precision, scheme, warm-start mode or "
+                "recording length than the context");
+  if (bytes < mine.total || h.total != mine.total)
+    return fail(BTE_E_STATE, "state has %zu bytes, expected %llu", bytes, mine.total);
+  for (int i = 0; i < kStateSections; ++i)
+    if (h.off[i] != mine.off[i]) return fail(BTE_E_STATE, "state section %d is misplaced", i);
+  const Shape& s = ctx->s;
+  const char* in = static_cast<const char*>(buf);
+  if (memcmp(in + h.off[kSecIref], ctx->Iref.data(), sizeof(double) * s.nb) != 0)
+    return fail(BTE_E_STATE, "the state's storage reference differs from the context's "
+                "(another coldest input temperature)");
+  if (h.nn_recorded < 0 || h.nn_recorded > h.nn_rec || h.nn_adam_t < 0 || h.steps < 0)
+    return fail(BTE_E_STATE, "state counters out of range");
+  const size_t nc = s.nc, rows = (size_t)s.nb * s.nd;
+  auto h2d = [&](void* dst, int sec, size_t n) {
+    return hipMemcpyAsync(dst, in + h.off[sec], n, hipMemcpyHostToDevice, ctx->stream);
+  };
+  HIP_TRY(hipMemcpy2DAsync(ctx->In, s.real_size * s.ncp, in + h.off[kSecI], s.real_size * nc,
+                           s.real_size * nc, rows, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(h2d(ctx->T, kSecT, sizeof(double) * nc));
+  HIP_TRY(h2d(ctx->Tprev, kSecTprev, sizeof(double) * nc));
+  HIP_TRY(h2d(ctx->E, kSecE, sizeof(double) * nc));
+  HIP_TRY(hipMemcpy2DAsync(ctx->I0, sizeof(double) * s.ncp, in + h.off[kSecI0],
+                           sizeof(double) * nc, sizeof(double) * nc, (size_t)s.nb,
+                           hipMemcpyHostToDevice, ctx->stream));
+  if (s.warm) {
+    const size_t P = (size_t)ctx->nnL.total;
+    HIP_TRY(h2d(ctx->nnB.params, kSecParams, sizeof(float) * P));
+    HIP_TRY(h2d(ctx->nnB.adam_m, kSecM, sizeof(float) * P));
+    HIP_TRY(h2d(ctx->nnB.adam_v, kSecV, sizeof(float) * P));
+    HIP_TRY(h2d(ctx->nnB.hist, kSecHist, sizeof(float) * 4 * (size_t)s.nn_rec * nc));
+    HIP_TRY(nn_refresh(ctx->stream, ctx->nnL, ctx->nnB));
+  }
+  // scattering rates at the restored temperatures (the formula of the
+  // temperature inversion, so the same bits)
+  if (ctx->t.relax) HIP_TRY(launch_equilibrium(ctx->stream, ctx->g, ctx->t, ctx->T, ctx->I0, nullptr));
+  HIP_TRY(launch_reset(ctx->stream, ctx->ctl));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  // host-side counters, and the layout the saved context swept with if this
+  // one can hold it (direction groups change the energy sum's grouping)
+  ctx->steps_taken = h.steps;
+  if (s.warm) {
+    const int* plain = reinterpret_cast<const int*>(in + h.off[kSecPlain]);
+    ctx->nn_plain_sweeps.assign(plain, plain + h.nn_recorded);
+    ctx->nn_nrec = h.nn_recorded;
+    ctx->nn_ready = h.nn_trained;
+    ctx->nn_off = h.nn_off;
+    ctx->nn_warm_steps = h.nn_warm_steps;
+    ctx->nn_warm_sweeps = h.nn_warm_sweeps;
+    ctx->nn_adam_t = h.nn_adam_t;
+    ctx->nn_last_batch = h.nn_last_batch > 0 ? h.nn_last_batch : 1;
+    ctx->nn_loss_pending = false;
+  }
+  auto family = [](int kind) { return kind == kSweepFlat3D ? (int)kSweepColumnWalk3D : kind; };
+  if (family(h.layout[0]) == family(s.plan.kind) &&
+      (h.layout[0] != s.plan.kind || h.layout[1] != s.plan.ry || h.layout[2] != s.plan.rz ||
+       h.layout[3] != s.plan.ndg)) {
+    const SweepPlan pl = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, h.layout[1],
+                                         h.layout[2], h.layout[3], h.layout[0]);
+    if (pl.kind == h.layout[0] && pl.ry == h.layout[1] && pl.rz == h.layout[2] &&
+        pl.ndg == h.layout[3] && pl.ndg <= s.ndg_cap && pl.nparts <= s.nparts_cap) {
+      ctx->s.plan = pl;
+      ctx->g.ndg = pl.ndg;
+    }
+  }
+  return BTE_OK;
+}
+
 
 static int nn_check(bte_ctx* ctx) {
   if (!ctx) return fail(BTE_E_INVAL, "null context");
@@ -1066,6 +1460,8 @@ int bte_destroy(bte_ctx* ctx) {
   for (auto e : ctx->t_start) (void)hipEventDestroy(e);
   for (auto e : ctx->t_stop) (void)hipEventDestroy(e);
   if (ctx->host_ring) (void)hipHostFree(ctx->host_ring);
+  if (ctx->host_steps) (void)hipHostFree(ctx->host_steps);
+  drop_step_graphs(ctx);
   delete ctx;
   return BTE_OK;
 }
@@ -1227,9 +1623,87 @@ struct bte_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   hipEvent_t ev[kRing];
+  // each context's sweep layout when the work lists were built: the lists,
+  // tile counts and partial indices hold only for these
+  std::vector<SweepPlan> plans;
 };
 
 namespace {
+
+// The device descriptor of one geometry for the next step of a batch.
+void fill_batch_ctx(BatchCtx& d, const bte_ctx* ctx, int cell_block0) {
+  memset(&d, 0, sizeof d);
+  d.sp64.g = ctx->g;
+  d.sp64.t = ctx->t;
+  d.sp64.In = static_cast<const double*>(ctx->In);
+  d.sp64.I0 = ctx->I0;
+  d.sp64.S = ctx->S;
+  d.sp64.part = ctx->part;
+  d.sp64.ctl = ctx->ctl;
+  d.sp64.inv_dt = 1.0 / ctx->opt.dt;
+  d.sp64.shift = nullptr;
+  d.sp32.g = ctx->g;
+  d.sp32.t = ctx->t;
+  d.sp32.In = static_cast<const float*>(ctx->In);
+  d.sp32.I0 = ctx->I0;
+  d.sp32.S = ctx->S;
+  d.sp32.part = ctx->part;
+  d.sp32.ctl = ctx->ctl;
+  d.sp32.inv_dt = 1.0 / ctx->opt.dt;
+  d.sp32.shift = nullptr;
+  d.plan = ctx->s.plan;
+  d.precision = ctx->opt.precision;
+  d.in_idx = 0;
+  d.F[0] = ctx->In;
+  d.F[1] = ctx->Ia;
+  d.F[2] = ctx->Ib;
+  d.I0 = ctx->I0;
+  d.S = ctx->S;
+  d.part = ctx->part;
+  d.T = ctx->T;
+  d.E = ctx->E;
+  d.ctl = ctx->ctl;
+  d.tol = ctx->opt.tol;
+  d.max_inner = ctx->opt.max_inner;
+  d.fixed_k = 0;
+  d.cell_block0 = cell_block0;
+  d.cell_blocks =
+      (ctx->s.nc + temp_cells_per_block(ctx->s.nb) - 1) / temp_cells_per_block(ctx->s.nb);
+}
+
+// The checks every batch applies to its contexts.
+int check_batch_members(int n, bte_ctx* const* ctxs) {
+  for (int i = 0; i < n; ++i) {
+    const bte_ctx* c = ctxs[i];
+    if (!c || c->poisoned) return fail(BTE_E_INVAL, "context %d is null or poisoned", i);
+    if (c->stream != ctxs[0]->stream) return fail(BTE_E_INVAL, "contexts must share one stream");
+    if (c->opt.precision != ctxs[0]->opt.precision)
+      return fail(BTE_E_INVAL, "contexts must share one precision");
+    if (c->opt.scheme != BTE_IMPLICIT_JACOBI)
+      return fail(BTE_E_INVAL, "batches run the implicit scheme");
+    if (c->s.warm == BTE_WARM_T_SHIFT)
+      return fail(BTE_E_INVAL, "batches seed warm starts through the temperature only");
+    const SweepPlan& pl = c->s.plan;
+    if (!batch_layout(pl.kind, pl.ry, pl.rz))
+      return fail(BTE_E_INVAL,
+                  "batches need the 4-row 2D, the 2x2 or 1x4 3D column-walk or the "
+                  "flattened-plane layout (context %d)", i);
+    if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
+    if (c->t.relax)
+      return fail(BTE_E_INVAL,
+                  "batches take constant relaxation times (context %d has a temperature law)", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(BTE_E_INVAL, "context %d appears twice", i);
+  }
+  return BTE_OK;
+}
+
+// Which work list a context's layout belongs to.
+int batch_list_of(const SweepPlan& pl) {
+  if (pl.kind == kSweepColumnWalk2D) return kList2D;
+  if (pl.kind == kSweepFlat3D && pl.rz == 4) return kListFlat4;
+  return kList3D;
+}
 
 int batch_fail_free(bte_batch* b, int code) {
   bte_batch_destroy(b);
@@ -1259,28 +1733,14 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   bte_ctx* ctx = nullptr;
   if (!out || n < 1 || !ctxs) return fail(BTE_E_INVAL, "need at least one context");
   *out = nullptr;
-  for (int i = 0; i < n; ++i) {
-    const bte_ctx* c = ctxs[i];
-    if (!c || c->poisoned) return fail(BTE_E_INVAL, "context %d is null or poisoned", i);
-    if (c->stream != ctxs[0]->stream) return fail(BTE_E_INVAL, "contexts must share one stream");
-    if (c->opt.precision != ctxs[0]->opt.precision)
-      return fail(BTE_E_INVAL, "contexts must share one precision");
-    if (c->opt.scheme != BTE_IMPLICIT_JACOBI)
-      return fail(BTE_E_INVAL, "batches run the implicit scheme");
-    if (c->s.warm == BTE_WARM_T_SHIFT)
-      return fail(BTE_E_INVAL, "batches seed warm starts through the temperature only");
-    const SweepPlan& pl = c->s.plan;
-    if (!batch_layout(pl.kind, pl.ry, pl.rz))
-      return fail(BTE_E_INVAL,
-                  "batches need the 4-row 2D, the 2x2 or 1x4 3D column-walk or the flattened-plane "
-      "layout (context %d)", i);
-    if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
-    for (int j = 0; j < i; ++j)
-      if (ctxs[j] == c) return fail(BTE_E_INVAL, "context %d appears twice", i);
+  {
+    const int rc = check_batch_members(n, ctxs);
+    if (rc != BTE_OK) return rc;
   }
   bte_batch* b = new (std::nothrow) bte_batch();
   if (!b) return fail(BTE_E_NOMEM, "out of host memory");
   b->ctx.assign(ctxs, ctxs + n);
+  for (int i = 0; i < n; ++i) b->plans.push_back(ctxs[i]->s.plan);
   b->stream = ctxs[0]->stream;
   b->precision = ctxs[0]->opt.precision;
   b->use_graph = use_graph != 0 && b->stream != nullptr;
@@ -1303,9 +1763,7 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
   std::vector<BatchItem> lists[kBatchLists];
   for (int i : order) {
     const SweepPlan& pl = ctxs[i]->s.plan;
-    auto& dst = pl.kind == kSweepColumnWalk2D                  ? lists[kList2D]
-                : (pl.kind == kSweepFlat3D && pl.rz == 4) ? lists[kListFlat4]
-                                                          : lists[kList3D];
+    auto& dst = lists[batch_list_of(pl)];
     const int nz = pl.ndg;  // direction groups
     for (int bz = 0; bz < nz; ++bz)
       for (int by = 0; by < ctxs[i]->s.nb; ++by)
@@ -1437,6 +1895,15 @@ int bte_batch_step(bte_batch* b, int nsteps, bte_step_stats* stats) {
   if (!b) return fail(BTE_E_INVAL, "null batch");
   if (nsteps < 0) return fail(BTE_E_INVAL, "nsteps must be >= 0");
   const int n = (int)b->ctx.size();
+  for (int i = 0; i < n; ++i) {
+    const SweepPlan& p = b->ctx[i]->s.plan;
+    const SweepPlan& q = b->plans[i];
+    if (p.kind != q.kind || p.ry != q.ry || p.rz != q.rz || p.ndg != q.ndg ||
+        p.ntiles != q.ntiles || p.nparts != q.nparts)
+      return fail(BTE_E_INVAL,
+                  "context %d changed its sweep layout after joining the batch (the batch's "
+                  "work lists are built for the old one): create the batch again", i);
+  }
   std::vector<StepState> ss(n);
   for (int step = 0; step < nsteps; ++step) {
     for (int i = 0; i < n; ++i) {
@@ -1444,44 +1911,8 @@ int bte_batch_step(bte_batch* b, int nsteps, bte_step_stats* stats) {
       if (ctx->poisoned) return fail(BTE_E_DEVICE, "context %d is poisoned", i);
       int rc = step_begin(ctx, 0, &ss[i]);
       if (rc != BTE_OK) return rc;
-      BatchCtx& d = b->h_ctx[i];
-      memset(&d, 0, sizeof d);
-      d.sp64.g = ctx->g;
-      d.sp64.t = ctx->t;
-      d.sp64.In = static_cast<const double*>(ctx->In);
-      d.sp64.I0 = ctx->I0;
-      d.sp64.S = ctx->S;
-      d.sp64.part = ctx->part;
-      d.sp64.ctl = ctx->ctl;
-      d.sp64.inv_dt = 1.0 / ctx->opt.dt;
-      d.sp64.shift = nullptr;
-      d.sp32.g = ctx->g;
-      d.sp32.t = ctx->t;
-      d.sp32.In = static_cast<const float*>(ctx->In);
-      d.sp32.I0 = ctx->I0;
-      d.sp32.S = ctx->S;
-      d.sp32.part = ctx->part;
-      d.sp32.ctl = ctx->ctl;
-      d.sp32.inv_dt = 1.0 / ctx->opt.dt;
-      d.sp32.shift = nullptr;
-      d.plan = ctx->s.plan;
-      d.precision = ctx->opt.precision;
-      d.in_idx = 0;
-      d.F[0] = ctx->In;
-      d.F[1] = ctx->Ia;
-      d.F[2] = ctx->Ib;
-      d.I0 = ctx->I0;
-      d.S = ctx->S;
-      d.part = ctx->part;
-      d.T = ctx->T;
-      d.E = ctx->E;
-      d.ctl = ctx->ctl;
-      d.tol = ctx->opt.tol;
-      d.max_inner = ctx->opt.max_inner;
-      d.fixed_k = 0;
-      d.cell_block0 = (i == 0) ? 0 : b->h_ctx[i - 1].cell_block0 + b->h_ctx[i - 1].cell_blocks;
-      d.cell_blocks =
-          (ctx->s.nc + temp_cells_per_block(ctx->s.nb) - 1) / temp_cells_per_block(ctx->s.nb);
+      fill_batch_ctx(b->h_ctx[i], ctx,
+                     (i == 0) ? 0 : b->h_ctx[i - 1].cell_block0 + b->h_ctx[i - 1].cell_blocks);
     }
     ctx = nullptr;
     HIP_TRY(hipMemcpyAsync(b->d_ctx, b->h_ctx, sizeof(BatchCtx) * n, hipMemcpyHostToDevice,

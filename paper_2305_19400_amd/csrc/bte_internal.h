@@ -99,12 +99,26 @@ struct Tables {
   const double* fweight;     // [nb] band weight of the temperature relation
   const double* Iref;        // [nb] storage reference: stored value = I - Iref[b]
                              // (zero in FP64 mode, I0_b(T_ref) in FP32 mode)
+  // Temperature-dependent relaxation (null / zero when tau is constant):
+  // 1/tau_b(T) = inv_tau[b] (T / tau_T0)^tau_p[b]; relax[b][cell] holds it at
+  // each cell's current temperature, refreshed with I0.
+  const double* tau_p;       // [nb] exponents
+  double* relax;             // [nb][ncp]
+  double tau_T0;
+  int tau_weighted;          // temperature definition weights bands by 1/tau_b(T)
+  int explicit_scheme;       // forward Euler (the update scale is dt)
   double W;                  // sum of the direction weights
   int wall[6];
   const double* wall_I0[6];  // [nb][nfaces] for isothermal walls, else null
   const void* wall_S[6];     // the same in intensity storage format (Real, minus Iref)
   int wall_nf[6];
 };
+
+// Scattering rate 1/tau_b(T) of a temperature-dependent relaxation time
+// tau_b(T) = tau_b (T0 / T)^p_b (Sec. 2.2: I0 and tau both depend on T).
+__device__ __forceinline__ double relax_rate(double inv_tau, double p, double T, double T0) {
+  return inv_tau * pow(T / T0, p);
+}
 
 // Everything one sweep launch reads: mesh, tables, the three intensity
 // fields of the iteration (current iterate, step start, new iterate), the
@@ -134,7 +148,7 @@ hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
                         const Control* ctl, const double* shift);
 
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
-                              const double* S, double* T, double* I0, double* E, Control* ctl);
+                              double* S, double* T, double* I0, double* E, Control* ctl);
 
 hipError_t launch_control(hipStream_t stream, int nparts, const double* part, double vol,
                           int fixed_k, int max_inner, double tol, int explicit_mode,
@@ -183,6 +197,15 @@ struct BatchControl {
 // with 4 planes (a kernel of its own, since it needs more registers).
 enum BatchList { kList2D = 0, kList3D = 1, kListFlat4 = 2, kBatchLists = 3 };
 
+// A work list described by its geometries' item ranges instead of stored
+// items: geometry ctx[j] owns items [start[j], start[j + 1]) of the list,
+// ordered direction group, band, tile (tile fastest).
+struct BatchRanges {
+  int n;             // geometries in the list
+  const int* ctx;    // [n] context index
+  const int* start;  // [n + 1] first item of each geometry, then the item count
+};
+
 // One inner iteration of every geometry: persistent sweep over the work list,
 // temperature inversion, per-geometry control, active count (+ reset of the
 // work counter for the next iteration).
@@ -191,10 +214,18 @@ hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* c
                                   int nctx, const BatchItem* items,
                                   const int counts[kBatchLists], BatchControl* bc,
                                   const int sweep_blocks[kBatchLists], int temp_blocks);
+// The same iteration with the work lists given as geometry ranges (no stored
+// items).
+hipError_t launch_batch_iteration_ranges(hipStream_t stream, int precision, BatchCtx* ctxs,
+                                         int nctx, const BatchRanges ranges[kBatchLists],
+                                         const int counts[kBatchLists], BatchControl* bc,
+                                         const int sweep_blocks[kBatchLists], int temp_blocks);
 hipError_t launch_batch_reset(hipStream_t stream, BatchCtx* ctxs, int nctx, BatchControl* bc);
 // Resident workgroups per compute unit of one list's persistent sweep kernel.
 int batch_sweep_occupancy(int precision, int list);
 
+// I0[b][P] = I0_b(T_P) (and t.relax at T_P if the relaxation times depend on
+// T); E_P = W sum_b I0_b(T_P) if E is given.
 hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Tables& t,
                               const double* T, double* I0, double* E);
 

@@ -153,6 +153,15 @@ __device__ __forceinline__ Real update_finish(A acc, A v, A scale) {
   else return static_cast<Real>(v + acc * scale);
 }
 
+// The update scale of a cell whose relaxation rate depends on its
+// temperature: 1 / (1/dt + rate + sum_axis c_axis), summed in the order of the
+// per-(direction, band) table's constant-rate diagonal; dt for forward Euler.
+__device__ __forceinline__ double cell_scale(const Coef& cf, double inv_dt, double rate,
+                                             int explicit_scheme) {
+  if (explicit_scheme) return cf.scale;
+  return 1.0 / ((((inv_dt + rate) + cf.c[0]) + cf.c[1]) + cf.c[2]);
+}
+
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const long long bits = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
@@ -252,7 +261,7 @@ __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t
 //   I^{k+1} = I^k + R * scale,   scale = 1/(1/dt + 1/tau_b + sum_axis c_axis)
 // Forward Euler passes I^k = I^n and scale = dt, which is Eq.
 // eq-conservation-discrete with the same upwind fluxes.
-template <typename Real, int DIM, bool SHIFT>
+template <typename Real, int DIM, bool SHIFT, bool TAUT>
 __device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int bx, const int by,
                                            const int gx) {
 #pragma clang fp contract(on)  // fuse a*b+c only within one expression
@@ -270,7 +279,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int
   const Real* __restrict__ Inb = p.In + band_off;
   Real* __restrict__ Iob = p.Iout + band_off;
   const double I0P = p.I0[(size_t)b * ncp + Pc];
-  const double inv_tau = cld(p.t.inv_tau, (size_t)b);
+  const double inv_tau = TAUT ? p.t.relax[(size_t)b * ncp + Pc] : cld(p.t.inv_tau, (size_t)b);
   const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
   const int slab_bytes = g.nc * (int)sizeof(Real);
   const int voff = Pc * (int)sizeof(Real);
@@ -335,7 +344,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int
       }
       acc += cf.c[a] * (up - ik);
     }
-    const Real inew_r = encode<Real>(iref, ik + acc * cf.scale);
+    const double scale = TAUT ? cell_scale(cf, p.inv_dt, inv_tau, p.t.explicit_scheme) : cf.scale;
+    const Real inew_r = encode<Real>(iref, ik + acc * scale);
     if (active) buf_store<Real>(inew_r, slab_rsrc(Iob + (size_t)d * ncp, slab_bytes), voff, 0);
     const double inew = decode(iref, inew_r);
     const double da = inew - ik;
@@ -371,10 +381,10 @@ __device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int
   }
 }
 
-template <typename Real, int DIM, bool SHIFT>
+template <typename Real, int DIM, bool SHIFT, bool TAUT>
 __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Real> p) {
   if (step_done(p.ctl)) return;
-  sweep_body<Real, DIM, SHIFT>(p, blockIdx.x, blockIdx.y, gridDim.x);
+  sweep_body<Real, DIM, SHIFT, TAUT>(p, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ---------------------------------------------------------------- 2D column walk
@@ -387,7 +397,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(const SweepParams<Re
 // tile edges read halo values (the x halo column is fetched by RY lanes in one
 // load and broadcast with readlane).  The per-(direction group, band, cell)
 // energy partials and per-workgroup norm partials are fused as in sweep_kernel.
-template <typename Real, int RY, bool SHIFT>
+template <typename Real, int RY, bool SHIFT, bool TAUT>
 __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const int ntx,
                                             const int dgs, const int bx, const int by,
                                             const int bz, const int gx, const int gy) {
@@ -432,7 +442,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   }
 
   using A = Arith<Real>;
-  A I0r[RY], sh[RY];
+  A I0r[RY], sh[RY], rate[RY];
   double S[RY], Sc[RY];
   {
     const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
@@ -442,6 +452,13 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
                                                           rowoff[j] / (int)sizeof(Real) * 8, 0);
       I0r[j] = to_arith<Real>(iref,
                               __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]));
+      rate[j] = inv_tau;
+      if constexpr (TAUT) {
+        const auto r2 = slab_rsrc(p.t.relax + (size_t)b * ncp, g.nc * 8);
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r2, (colok ? lane : 0) * 8,
+                                                            rowoff[j] / (int)sizeof(Real) * 8, 0);
+        rate[j] = __longlong_as_double(((long long)u[1] << 32) | (unsigned int)u[0]);
+      }
       S[j] = 0.0;
       Sc[j] = 0.0;
       sh[j] = 0;
@@ -567,7 +584,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
       const A exj = read_lane(ex, j);
       if (colok && j < nrows) {
         const A v = ik[j];
-        A acc = update_start<Real>(in[j], I0r[j], v, a_inv_dt, a_inv_tau);
+        A acc = update_start<Real>(in[j], I0r[j], v, a_inv_dt, TAUT ? rate[j] : a_inv_tau);
         if (xpos) {
           const A up = lane == 0 ? exj : nbr;
           acc = update_add<Real>(acc, c0, up, v);
@@ -584,7 +601,8 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
         }
         // the stored value drives the norms and the energy: once the
         // iterate stops changing in storage precision its increment is zero
-        const Real inew_r = update_finish<Real>(acc, v, scale);
+        const A sc = TAUT ? cell_scale(cf, p.inv_dt, rate[j], p.t.explicit_scheme) : scale;
+        const Real inew_r = update_finish<Real>(acc, v, sc);
         buf_store<Real>(inew_r, ro, vrow[j], 0);
         const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
@@ -628,11 +646,11 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   }
 }
 
-template <typename Real, int RY, bool SHIFT>
+template <typename Real, int RY, bool SHIFT, bool TAUT>
 __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepParams<Real> p,
                                                                    const int ntx, const int dgs) {
   if (step_done(p.ctl)) return;
-  walk2d_body<Real, RY, SHIFT>(p, ntx, dgs, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
+  walk2d_body<Real, RY, SHIFT, TAUT>(p, ntx, dgs, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
                                gridDim.y);
 }
 
@@ -647,7 +665,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep2d_walk_kernel(const SweepPa
 // is one load from a wave-uniformly chosen buffer like any slab value) or the
 // wall cell's own intensity in the mirrored direction.  Every load of a
 // direction is issued before the first wait.
-template <typename Real, int RY, int RZ, bool SHIFT>
+template <typename Real, int RY, int RZ, bool SHIFT, bool TAUT>
 __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const int ntx,
                                             const int nty, const int dgs, const int bx,
                                             const int by, const int bz, const int gx,
@@ -697,7 +715,7 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
     for (int k = 0; k < RZ; ++k) vc[j][k] = ((zp[k] * ny + yr[j]) * nx + xcol) * sz;
 
   using A = Arith<Real>;
-  A I0r[RY][RZ], sh[RY][RZ];
+  A I0r[RY][RZ], sh[RY][RZ], rate[RY][RZ];
   double S[RY][RZ], Sc[RY][RZ];
   {
     const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
@@ -706,6 +724,10 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
         I0r[j][k] = to_arith<Real>(iref, buf_load_raw<double>(r0, vc[j][k] / sz * 8));
+        rate[j][k] = inv_tau;
+        if constexpr (TAUT)
+          rate[j][k] = buf_load_raw<double>(slab_rsrc(p.t.relax + (size_t)b * ncp, g.nc * 8),
+                                            vc[j][k] / sz * 8);
         S[j][k] = 0.0;
         Sc[j][k] = 0.0;
         sh[j][k] = 0;
@@ -863,7 +885,8 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
         const A exjk = read_lane(ex, j + RY * k);
         if (colok && j < nrows && k < nplanes) {
           const A v = ik[j][k];
-          A acc = update_start<Real>(in[j][k], I0r[j][k], v, a_inv_dt, a_inv_tau);
+          A acc = update_start<Real>(in[j][k], I0r[j][k], v, a_inv_dt,
+                                     TAUT ? rate[j][k] : a_inv_tau);
           if (xpos) {
             const A up = lane == 0 ? exjk : nbr;
             acc = update_add<Real>(acc, c0, up, v);
@@ -887,7 +910,9 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
           }
           // the stored value drives the norms and the energy: once the
           // iterate stops changing in storage precision its increment is zero
-          const Real inew_r = update_finish<Real>(acc, v, scale);
+          const A sc =
+              TAUT ? cell_scale(cf, p.inv_dt, rate[j][k], p.t.explicit_scheme) : scale;
+          const Real inew_r = update_finish<Real>(acc, v, sc);
           buf_store<Real>(inew_r, ro, vc[j][k], 0);
           const A inew = inew_r;
           const double da = static_cast<double>(inew - v);
@@ -935,12 +960,12 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
   }
 }
 
-template <typename Real, int RY, int RZ, bool SHIFT>
+template <typename Real, int RY, int RZ, bool SHIFT, bool TAUT>
 __global__ __launch_bounds__(kSweepBlock) void sweep3d_walk_kernel(const SweepParams<Real> p,
                                                                    const int ntx, const int nty,
                                                                    const int dgs) {
   if (step_done(p.ctl)) return;
-  walk3d_body<Real, RY, RZ, SHIFT>(p, ntx, nty, dgs, blockIdx.x, blockIdx.y, blockIdx.z,
+  walk3d_body<Real, RY, RZ, SHIFT, TAUT>(p, ntx, nty, dgs, blockIdx.x, blockIdx.y, blockIdx.z,
                                    gridDim.x, gridDim.y);
 }
 
@@ -955,7 +980,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep3d_walk_kernel(const SweepPa
 // away, which this or the previous wave has just read.  Lanes on an x or y
 // wall take the ghost (isothermal equilibrium in storage format, or the
 // cell's own intensity in the mirrored direction) from a load masked to them.
-template <typename Real, int RZ, bool SHIFT>
+template <typename Real, int RZ, bool SHIFT, bool TAUT>
 __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const int nft,
                                             const int dgs, const int bx, const int by,
                                             const int bz, const int gx, const int gy) {
@@ -1010,7 +1035,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
   const int pl_p = wall_zp ? 0 : z0 - 1;
   const int pl_n = wall_zn ? nz - 1 : z0 + nplanes;
 
-  A I0r[RZ], sh[RZ];
+  A I0r[RZ], sh[RZ], rate[RZ];
   double S[RZ], Sc[RZ];
   A shy_p[RZ], shy_n[RZ];
   A shx_p = 0, shx_n = 0, shz_p = 0, shz_n = 0;
@@ -1019,6 +1044,10 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
 #pragma unroll
     for (int k = 0; k < RZ; ++k) {
       I0r[k] = to_arith<Real>(iref, buf_load_raw<double>(r0, vc[k] / sz * 8));
+      rate[k] = inv_tau;
+      if constexpr (TAUT)
+        rate[k] = buf_load_raw<double>(slab_rsrc(p.t.relax + (size_t)b * ncp, g.nc * 8),
+                                       vc[k] / sz * 8);
       S[k] = 0.0;
       Sc[k] = 0.0;
       sh[k] = 0;
@@ -1130,7 +1159,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
       if constexpr (SHIFT) ey += ypos ? shy_p[k] : shy_n[k];
       if (fok && k < nplanes) {
         const A v = ik[k];
-        A acc = update_start<Real>(in[k], I0r[k], v, a_inv_dt, a_inv_tau);
+        A acc = update_start<Real>(in[k], I0r[k], v, a_inv_dt, TAUT ? rate[k] : a_inv_tau);
         if (xpos || xneg) {
           const A up = xw ? xg[k] : (lane == edge_lane ? exk : nbr);
           acc = update_add<Real>(acc, c0, up, v);
@@ -1148,7 +1177,8 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
         }
         // the stored value drives the norms and the energy: once the
         // iterate stops changing in storage precision its increment is zero
-        const Real inew_r = update_finish<Real>(acc, v, scale);
+        const A sc = TAUT ? cell_scale(cf, p.inv_dt, rate[k], p.t.explicit_scheme) : scale;
+        const Real inew_r = update_finish<Real>(acc, v, sc);
         buf_store<Real>(inew_r, ro, vc[k], 0);
         const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
@@ -1185,7 +1215,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
   }
 }
 
-template <typename Real, int RZ, bool SHIFT>
+template <typename Real, int RZ, bool SHIFT, bool TAUT>
 __global__ __launch_bounds__(kSweepBlock) void sweep3d_flat_kernel(const SweepParams<Real> p,
                                                                    const int nft, const int dgs) {
   if (step_done(p.ctl)) return;
@@ -1199,7 +1229,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep3d_flat_kernel(const SweepPa
     const int per_xcd = gridDim.x >> 3;
     bx = (bx & 7) * per_xcd + (bx >> 3);
   }
-  flat3d_body<Real, RZ, SHIFT>(p, nft, dgs, bx, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
+  flat3d_body<Real, RZ, SHIFT, TAUT>(p, nft, dgs, bx, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
 SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int rz,
@@ -1258,22 +1288,22 @@ SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int r
   return pl;
 }
 
-template <typename Real, bool SHIFT>
+template <typename Real, bool SHIFT, bool TAUT>
 static void launch_sweep_t(hipStream_t stream, const SweepPlan& plan, const SweepParams<Real>& p) {
   const Geometry& g = p.g;
   if (plan.kind == kSweepColumnWalk2D) {
     const dim3 grid(plan.ntiles, g.nb, plan.ndg);
     switch (plan.ry) {
       case 4:
-        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 4, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                            stream, p, plan.ntx, plan.dgs);
         break;
       case 8:
-        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 8, SHIFT>), grid, dim3(kSweepBlock), 0,
+        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 8, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                            stream, p, plan.ntx, plan.dgs);
         break;
       default:
-        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 16, SHIFT>), grid, dim3(kSweepBlock), 0,
+        hipLaunchKernelGGL((sweep2d_walk_kernel<Real, 16, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                            stream, p, plan.ntx, plan.dgs);
         break;
     }
@@ -1282,31 +1312,31 @@ static void launch_sweep_t(hipStream_t stream, const SweepPlan& plan, const Swee
   if (plan.kind == kSweepFlat3D) {
     const dim3 grid(plan.ntiles, g.nb, plan.ndg);
     if (plan.rz == 2)
-      hipLaunchKernelGGL((sweep3d_flat_kernel<Real, 2, SHIFT>), grid, dim3(kSweepBlock), 0,
+      hipLaunchKernelGGL((sweep3d_flat_kernel<Real, 2, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                          stream, p, plan.ntx, plan.dgs);
     else
-      hipLaunchKernelGGL((sweep3d_flat_kernel<Real, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+      hipLaunchKernelGGL((sweep3d_flat_kernel<Real, 4, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                          stream, p, plan.ntx, plan.dgs);
     return;
   }
   if (plan.kind == kSweepColumnWalk3D) {
     const dim3 grid(plan.ntiles, g.nb, plan.ndg);
     if (plan.rz == 4 && plan.ry == 1)
-      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 1, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 1, 4, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                          stream, p, plan.ntx, plan.nty, plan.dgs);
     else if (plan.rz == 4)
-      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 2, 4, SHIFT>), grid, dim3(kSweepBlock), 0,
+      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 2, 4, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                          stream, p, plan.ntx, plan.nty, plan.dgs);
     else
-      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 2, 2, SHIFT>), grid, dim3(kSweepBlock), 0,
+      hipLaunchKernelGGL((sweep3d_walk_kernel<Real, 2, 2, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0,
                          stream, p, plan.ntx, plan.nty, plan.dgs);
     return;
   }
   const dim3 grid(plan.ntiles, g.nb);
   if (g.dim == 3)
-    hipLaunchKernelGGL((sweep_kernel<Real, 3, SHIFT>), grid, dim3(kSweepBlock), 0, stream, p);
+    hipLaunchKernelGGL((sweep_kernel<Real, 3, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0, stream, p);
   else
-    hipLaunchKernelGGL((sweep_kernel<Real, 2, SHIFT>), grid, dim3(kSweepBlock), 0, stream, p);
+    hipLaunchKernelGGL((sweep_kernel<Real, 2, SHIFT, TAUT>), grid, dim3(kSweepBlock), 0, stream, p);
 }
 
 template <typename Real>
@@ -1315,8 +1345,13 @@ hipError_t launch_sweep(hipStream_t stream, const Geometry& g, const Tables& t,
                         Real* Iout, const double* I0, double* S, double* part,
                         const Control* ctl, const double* shift) {
   const SweepParams<Real> p{g, t, Ik, In, Iout, I0, S, part, ctl, inv_dt, shift};
-  if (shift) launch_sweep_t<Real, true>(stream, plan, p);
-  else launch_sweep_t<Real, false>(stream, plan, p);
+  if (t.relax) {
+    if (shift) launch_sweep_t<Real, true, true>(stream, plan, p);
+    else launch_sweep_t<Real, false, true>(stream, plan, p);
+  } else {
+    if (shift) launch_sweep_t<Real, true, false>(stream, plan, p);
+    else launch_sweep_t<Real, false, false>(stream, plan, p);
+  }
   return hipGetLastError();
 }
 
@@ -1367,13 +1402,42 @@ __device__ __forceinline__ void relation_part(const Tables& t, int nb, int l, do
   dF = t.W * df;
 }
 
+// With temperature-dependent relaxation times: partial sums over this lane's
+// bands of N(T) = W sum_b I0_b(T) / tau_b(T), D(T) = sum_b e_b / tau_b(T)
+// and their T-derivatives (d/dT 1/tau_b(T) = p_b / (T tau_b(T))); e_b is read
+// from E0[b * stride].
+template <int LANES>
+__device__ __forceinline__ void relation_part_tau(const Tables& t, int nb, int l, double T,
+                                                  const double* E0, size_t stride, double& N,
+                                                  double& dN, double& D, double& dD) {
+#pragma clang fp contract(off)
+  double n = 0.0, dn = 0.0, d = 0.0, dd = 0.0;
+  for (int b = l; b < nb; b += LANES) {
+    const double r = relax_rate(t.inv_tau[b], t.tau_p[b], T, t.tau_T0);
+    const double dr = t.tau_p[b] / T * r;
+    const double x = t.xfac[b] / T;
+    const double em1 = expm1(x);
+    const double i0 = t.Cb[b] / em1;
+    const double di0 = i0 * (x / T) * (em1 + 1.0) / em1;
+    const double e = E0[(size_t)b * stride];
+    n += r * i0;
+    dn += dr * i0 + r * di0;
+    d += r * e;
+    dd += dr * e;
+  }
+  N = t.W * n;
+  dN = t.W * dn;
+  D = d;
+  dD = dd;
+}
+
 // Per cell: finalise the energy sums from the per-(direction group, band)
 // partials, invert the temperature relation by Newton from the current T
 // (accept-first, quadratic convergence; Sec. 2.2 and Sec. 3.2 temperature
 // update), then refresh the equilibrium intensities I0[b][P] for the next sweep.
 template <int LANES>
 __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables& t,
-                                                 const double* __restrict__ S,
+                                                 double* __restrict__ S,
                                                  double* __restrict__ T, double* __restrict__ I0,
                                                  double* __restrict__ E, Control* ctl,
                                                  const int bx) {
@@ -1383,6 +1447,7 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
   const bool active = P < g.nc;
   const int Pc = active ? P : 0;
   const size_t ncp = (size_t)g.ncp;
+  const bool tau_newton = t.relax != nullptr && t.tau_weighted;
   CompSum Gs, Es;
   if (active) {
     // The partials of up to kChunk of this lane's bands are requested
@@ -1409,6 +1474,10 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
         if (b < g.nb) {
           Gs.add(t.fweight[b] * s[i].value());
           Es.add(s[i].value());
+          // temperature-dependent weights: the Newton iterations below re-read
+          // each band's sum, kept in the first group's partial (the next
+          // sweep rewrites it)
+          if (tau_newton) S[(size_t)b * ncp + Pc] = s[i].value();
         }
       }
     }
@@ -1419,7 +1488,36 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
   double Tc = T[Pc];
   int it = 0;
   bool ok = (G > 0.0) && isfinite(G) && (Tc > 0.0);
-  if (ok) {
+  if (tau_newton) {
+    // The relaxation-time-weighted temperature with tau_b(T): the root of
+    // K(T) = N(T) / D(T) - 1 (Newton, accept-first, same stopping rule).
+    ok = Tc > 0.0;
+    const double* E0 = S + Pc;
+    for (int k = 0; ok; ++k) {
+      double Np, dNp, Dp, dDp;
+      relation_part_tau<LANES>(t, g.nb, l, Tc, E0, ncp, Np, dNp, Dp, dDp);
+      const double N = group_sum<LANES>(Np), dN = group_sum<LANES>(dNp);
+      const double D = group_sum<LANES>(Dp), dD = group_sum<LANES>(dDp);
+      if (!(D > 0.0) || !isfinite(D)) {
+        ok = false;
+        break;
+      }
+      const double K = N / D - 1.0;
+      if (k == 0 && fabs(K) <= kNewtonAcceptRel) break;
+      if (k == kNewtonMaxIters) {
+        ok = false;
+        break;
+      }
+      const double dT = K / ((dN * D - N * dD) / (D * D));
+      Tc -= dT;
+      it = k + 1;
+      if (!isfinite(Tc) || !(Tc > 0.0)) {
+        ok = false;
+        break;
+      }
+      if (fabs(dT) <= kNewtonStepRel * Tc) break;
+    }
+  } else if (ok) {
     double Fp, dFp;
     relation_part<LANES>(t, g.nb, l, Tc, Fp, dFp);
     double F = group_sum<LANES>(Fp), dF = group_sum<LANES>(dFp);
@@ -1447,6 +1545,9 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
 #pragma unroll 4
   for (int b = l; b < g.nb; b += LANES)
     I0[(size_t)b * ncp + P] = equilibrium(t.Cb[b], t.xfac[b], Tc);
+  if (t.relax)
+    for (int b = l; b < g.nb; b += LANES)
+      t.relax[(size_t)b * ncp + P] = relax_rate(t.inv_tau[b], t.tau_p[b], Tc, t.tau_T0);
   if (l == 0) {
     T[P] = Tc;
     E[P] = En;
@@ -1456,7 +1557,7 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
 
 template <int LANES>
 __global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
-                                                          const double* __restrict__ S,
+                                                          double* __restrict__ S,
                                                           double* __restrict__ T,
                                                           double* __restrict__ I0,
                                                           double* __restrict__ E, Control* ctl) {
@@ -1465,7 +1566,7 @@ __global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
 }
 
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
-                              const double* S, double* T, double* I0, double* E, Control* ctl) {
+                              double* S, double* T, double* I0, double* E, Control* ctl) {
   const int cells_per_block = temp_cells_per_block(g.nb);
   const dim3 grid((g.nc + cells_per_block - 1) / cells_per_block);
   if (temp_lanes(g.nb) == 4)
@@ -1567,6 +1668,7 @@ __global__ __launch_bounds__(kCellBlock) void equilibrium_kernel(Geometry g, Tab
     const double v = equilibrium(t.Cb[b], t.xfac[b], Tc);
     I0[(size_t)b * g.ncp + P] = v;
     sum += v;
+    if (t.relax) t.relax[(size_t)b * g.ncp + P] = relax_rate(t.inv_tau[b], t.tau_p[b], Tc, t.tau_T0);
   }
   if (E) E[P] = t.W * sum;
 }
@@ -1717,16 +1819,16 @@ __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w
   const SweepParams<Real>& p = batch_params<Real>(c);
   const SweepPlan& pl = c.plan;
   if constexpr (LIST == kList2D)
-    walk2d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+    walk2d_body<Real, 4, false, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else if constexpr (LIST == kListFlat4)
-    flat3d_body<Real, 4, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+    flat3d_body<Real, 4, false, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else if (__builtin_amdgcn_readfirstlane(pl.kind) == kSweepFlat3D)
-    flat3d_body<Real, 2, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
+    flat3d_body<Real, 2, false, false>(p, pl.ntx, pl.dgs, w.bx, w.by, w.bz, pl.ntiles, p.g.nb);
   else if (__builtin_amdgcn_readfirstlane(pl.ry) == 1)
-    walk3d_body<Real, 1, 4, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
+    walk3d_body<Real, 1, 4, false, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
                                    p.g.nb);
   else
-    walk3d_body<Real, 2, 2, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
+    walk3d_body<Real, 2, 2, false, false>(p, pl.ntx, pl.nty, pl.dgs, w.bx, w.by, w.bz, pl.ntiles,
                                    p.g.nb);
 }
 
@@ -1742,9 +1844,14 @@ __device__ __forceinline__ void batch_item(const BatchCtx& c, const BatchItem& w
 // makes the loop's continuation divergent: lanes other than thread 0 then
 // circle the barrier re-reading a stale item while thread 0 waits outside the
 // inner loop, and the kernel never finishes.
-template <typename Real, int LIST>
+//
+// The items come from a stored list, or (decoded) from the list's geometry
+// ranges: geometry j of the list owns items [start[j], start[j + 1]), ordered
+// direction group, band, tile (tile fastest), as the stored lists are.
+template <typename Real, int LIST, bool DECODE>
 __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx* __restrict__ ctxs,
                                                                   const BatchItem* __restrict__ items,
+                                                                  const BatchRanges ranges,
                                                                   int nitems, int* next_item) {
   __shared__ int item_s;
   if (threadIdx.x == 0) item_s = atomicAdd(next_item, 1);
@@ -1755,10 +1862,30 @@ __global__ __launch_bounds__(kSweepBlock) void batch_sweep_kernel(const BatchCtx
     __syncthreads();  // every lane has read it before thread 0 claims the next one
     if (it >= nitems) break;
     BatchItem w;
-    w.ctx = __builtin_amdgcn_readfirstlane(items[it].ctx);
-    w.bx = __builtin_amdgcn_readfirstlane(items[it].bx);
-    w.by = __builtin_amdgcn_readfirstlane(items[it].by);
-    w.bz = __builtin_amdgcn_readfirstlane(items[it].bz);
+    if constexpr (DECODE) {
+      // the list's geometry holding item it: how many ranges start at or
+      // before it, less one (starts ascend), 64 at a time by a ballot
+      int j = -1;
+      for (int g0 = 0; g0 < ranges.n; g0 += 64) {
+        const int q = g0 + (int)(threadIdx.x & 63);
+        const unsigned long long m = __ballot(q < ranges.n && ranges.start[q] <= it);
+        j += __popcll(m);
+        if (m != ~0ull) break;
+      }
+      j = __builtin_amdgcn_readfirstlane(max(j, 0));
+      w.ctx = __builtin_amdgcn_readfirstlane(ranges.ctx[j]);
+      const int r = it - __builtin_amdgcn_readfirstlane(ranges.start[j]);
+      const int ntiles = __builtin_amdgcn_readfirstlane(ctxs[w.ctx].plan.ntiles);
+      const int nb = __builtin_amdgcn_readfirstlane(ctxs[w.ctx].sp64.g.nb);
+      w.bx = r % ntiles;
+      w.by = (r / ntiles) % nb;
+      w.bz = r / (ntiles * nb);
+    } else {
+      w.ctx = __builtin_amdgcn_readfirstlane(items[it].ctx);
+      w.bx = __builtin_amdgcn_readfirstlane(items[it].bx);
+      w.by = __builtin_amdgcn_readfirstlane(items[it].by);
+      w.bz = __builtin_amdgcn_readfirstlane(items[it].bz);
+    }
     const BatchCtx& c = ctxs[w.ctx];
     if (!step_done(c.ctl)) batch_item<Real, LIST>(c, w);
     if (threadIdx.x == 0) item_s = atomicAdd(next_item, 1);
@@ -1846,37 +1973,59 @@ __global__ void batch_reset_kernel(BatchCtx* ctxs, int nctx, BatchControl* bc) {
   }
 }
 
-template <typename Real>
+template <typename Real, bool DECODE>
 static void launch_batch_sweeps(hipStream_t stream, const BatchCtx* ctxs, const BatchItem* items,
-                                const int counts[kBatchLists], BatchControl* bc,
-                                const int blocks[kBatchLists]) {
+                                const BatchRanges* ranges, const int counts[kBatchLists],
+                                BatchControl* bc, const int blocks[kBatchLists]) {
   // each work list is consumed by its own persistent launch, compiled for
   // that list's layouts only, so no list pays another's registers
   const BatchItem* list = items;
+  const BatchRanges none{0, nullptr, nullptr};
   if (counts[kList2D] > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, kList2D>), dim3(blocks[kList2D]),
-                       dim3(kSweepBlock), 0, stream, ctxs, list, counts[kList2D], &bc->next_item);
-  list += counts[kList2D];
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kList2D, DECODE>), dim3(blocks[kList2D]),
+                       dim3(kSweepBlock), 0, stream, ctxs, list,
+                       DECODE ? ranges[kList2D] : none, counts[kList2D], &bc->next_item);
+  if (!DECODE) list += counts[kList2D];
   if (counts[kList3D] > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, kList3D>), dim3(blocks[kList3D]),
-                       dim3(kSweepBlock), 0, stream, ctxs, list, counts[kList3D],
-                       &bc->next_item3d);
-  list += counts[kList3D];
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kList3D, DECODE>), dim3(blocks[kList3D]),
+                       dim3(kSweepBlock), 0, stream, ctxs, list,
+                       DECODE ? ranges[kList3D] : none, counts[kList3D], &bc->next_item3d);
+  if (!DECODE) list += counts[kList3D];
   if (counts[kListFlat4] > 0)
-    hipLaunchKernelGGL((batch_sweep_kernel<Real, kListFlat4>), dim3(blocks[kListFlat4]),
-                       dim3(kSweepBlock), 0, stream, ctxs, list, counts[kListFlat4],
+    hipLaunchKernelGGL((batch_sweep_kernel<Real, kListFlat4, DECODE>), dim3(blocks[kListFlat4]),
+                       dim3(kSweepBlock), 0, stream, ctxs, list,
+                       DECODE ? ranges[kListFlat4] : none, counts[kListFlat4],
                        &bc->next_item_f4);
+}
+
+static void launch_batch_rest(hipStream_t stream, BatchCtx* ctxs, int nctx, BatchControl* bc,
+                              int temp_blocks) {
+  hipLaunchKernelGGL(batch_temperature_kernel, dim3(temp_blocks), dim3(256), 0, stream, ctxs, nctx);
+  hipLaunchKernelGGL(batch_control_kernel, dim3(nctx), dim3(kReduceBlock), 0, stream, ctxs);
+  hipLaunchKernelGGL(batch_count_kernel, dim3(1), dim3(64), 0, stream, ctxs, nctx, bc);
 }
 
 hipError_t launch_batch_iteration(hipStream_t stream, int precision, BatchCtx* ctxs,
                                   int nctx, const BatchItem* items,
                                   const int counts[kBatchLists], BatchControl* bc,
                                   const int sweep_blocks[kBatchLists], int temp_blocks) {
-  if (precision == 0) launch_batch_sweeps<double>(stream, ctxs, items, counts, bc, sweep_blocks);
-  else launch_batch_sweeps<float>(stream, ctxs, items, counts, bc, sweep_blocks);
-  hipLaunchKernelGGL(batch_temperature_kernel, dim3(temp_blocks), dim3(256), 0, stream, ctxs, nctx);
-  hipLaunchKernelGGL(batch_control_kernel, dim3(nctx), dim3(kReduceBlock), 0, stream, ctxs);
-  hipLaunchKernelGGL(batch_count_kernel, dim3(1), dim3(64), 0, stream, ctxs, nctx, bc);
+  if (precision == 0)
+    launch_batch_sweeps<double, false>(stream, ctxs, items, nullptr, counts, bc, sweep_blocks);
+  else
+    launch_batch_sweeps<float, false>(stream, ctxs, items, nullptr, counts, bc, sweep_blocks);
+  launch_batch_rest(stream, ctxs, nctx, bc, temp_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_iteration_ranges(hipStream_t stream, int precision, BatchCtx* ctxs,
+                                         int nctx, const BatchRanges ranges[kBatchLists],
+                                         const int counts[kBatchLists], BatchControl* bc,
+                                         const int sweep_blocks[kBatchLists], int temp_blocks) {
+  if (precision == 0)
+    launch_batch_sweeps<double, true>(stream, ctxs, nullptr, ranges, counts, bc, sweep_blocks);
+  else
+    launch_batch_sweeps<float, true>(stream, ctxs, nullptr, ranges, counts, bc, sweep_blocks);
+  launch_batch_rest(stream, ctxs, nctx, bc, temp_blocks);
   return hipGetLastError();
 }
 
@@ -1890,13 +2039,13 @@ static hipError_t list_occupancy(int* n, int list) {
   switch (list) {
     case kList2D:
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          n, batch_sweep_kernel<Real, kList2D>, kSweepBlock, 0);
+          n, batch_sweep_kernel<Real, kList2D, false>, kSweepBlock, 0);
     case kList3D:
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          n, batch_sweep_kernel<Real, kList3D>, kSweepBlock, 0);
+          n, batch_sweep_kernel<Real, kList3D, false>, kSweepBlock, 0);
     default:
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          n, batch_sweep_kernel<Real, kListFlat4>, kSweepBlock, 0);
+          n, batch_sweep_kernel<Real, kListFlat4, false>, kSweepBlock, 0);
   }
 }
 

@@ -529,6 +529,7 @@ __global__ __launch_bounds__(64) void apply_guess_kernel(Geometry g, Tables t, c
     const double old = I0[(size_t)b * g.ncp + P];
     const double nw = t.Cb[b] / expm1(t.xfac[b] / T0);
     I0[(size_t)b * g.ncp + P] = nw;
+    if (t.relax) t.relax[(size_t)b * g.ncp + P] = relax_rate(t.inv_tau[b], t.tau_p[b], T0, t.tau_T0);
     if (shift) shift[(size_t)b * g.ncp + P] = nw - old;
   }
 }

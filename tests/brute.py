@@ -111,40 +111,67 @@ def jacobi_sweep(inst, I_k, I_n, T_k, dt):
     return (Ik + (rhs - L @ Ik) / np.diag(L)).reshape(nc, nd, nb)
 
 
+def scattering_rate(inst, T):
+    """1/tau_b at the cell temperatures T, [..., N_b]: the relaxation time
+    tau_b (T0 / T)^p_b of a temperature-dependent instance, else tau_b."""
+    T = np.asarray(T, dtype=complex if np.iscomplexobj(T) else float)[..., None]
+    p = getattr(inst, "tau_exp", None)
+    if p is None:
+        return np.broadcast_to(1.0 / inst.tau, T.shape[:-1] + inst.tau.shape) + 0.0 * T
+    return (T / getattr(inst, "tau_T0", 300.0)) ** p / inst.tau
+
+
 def solve_backward_euler(inst, I_n, T_n, dt, t_energy=False, iters=30):
     """Solve one backward-Euler step exactly by Newton on the full system.
 
     I_n: [N_c, N_d, N_b]; T_n: [N_c].  Returns (I, T) at the new time level.
+    The relaxation term of row (P, d, b) is (I0_b(T_P) - I) / tau_b(T_P); the
+    cell's temperature equation is sum_b wgt_b(T_P) (W I0_b(T_P) - e_b) = 0 with
+    e_b = sum_d w_d I and wgt_b = 1/tau_b(T) (or 1 for the plain energy sum).
+    Temperature derivatives are taken by complex steps.
     """
     nx, ny, nz = inst.n
     nc, nd, nb = nx * ny * nz, inst.s.shape[0], inst.omega.shape[0]
     ndof = nc * nd * nb
     L, src = assemble(inst, dt)
-    wgt = np.ones(nb) if t_energy else 1.0 / inst.tau
+    # the assembled diagonal holds the constant 1/tau_b: take it out, the
+    # relaxation is added at the current temperature below
+    L0 = L - np.diag(np.broadcast_to((1.0 / inst.tau)[None, None, :], (nc, nd, nb)).reshape(-1))
     W = inst.w.sum()
+
+    def rates(T):
+        return scattering_rate(inst, T)  # [nc, nb]
+
+    def weights(T):
+        return np.ones((len(T), nb)) if t_energy else rates(T)
 
     I = I_n.reshape(-1).copy()
     T = T_n.copy()
     rhs_n = I_n.reshape(-1) / dt + src
     for _ in range(iters):
         eq = equilibrium(inst, T)  # [nc, nb]
-        eq_src = np.broadcast_to(eq[:, None, :], (nc, nd, nb)).reshape(-1)
-        tau_rep = np.broadcast_to(inst.tau[None, None, :], (nc, nd, nb)).reshape(-1)
-        rI = L @ I - rhs_n - eq_src / tau_rep
+        phi = rates(T)
+        wgt = weights(T)
+        rep = lambda a: np.broadcast_to(a[:, None, :], (nc, nd, nb)).reshape(-1)  # noqa: E731
+        rI = L0 @ I - rhs_n + rep(phi) * (I - rep(eq))
         Ir = I.reshape(nc, nd, nb)
-        G = np.einsum("d,b,pdb->p", inst.w, wgt, Ir)
-        F = W * (wgt[None, :] * eq).sum(axis=1)
-        rT = F - G
-        # complex-step derivative of the equilibrium in T
+        e = np.einsum("d,pdb->pb", inst.w, Ir)
+        rT = (wgt * (W * eq - e)).sum(axis=1)
+        # complex-step derivatives in T
         hstep = 1e-20 * T
-        deq = equilibrium(inst, T + 1j * hstep).imag / hstep[:, None]  # [nc, nb]
+        Tc = T + 1j * hstep
+        deq = equilibrium(inst, Tc).imag / hstep[:, None]  # [nc, nb]
+        dphi = rates(Tc).imag / hstep[:, None]
+        dwgt = weights(Tc).imag / hstep[:, None]
         J = np.zeros((ndof + nc, ndof + nc))
-        J[:ndof, :ndof] = L
+        J[:ndof, :ndof] = L0 + np.diag(rep(phi))
         for P in range(nc):
             rows = np.arange(P * nd * nb, (P + 1) * nd * nb)
-            J[rows, ndof + P] = -np.tile(deq[P] / inst.tau, nd)
-            J[ndof + P, rows] = -np.outer(inst.w, wgt).reshape(-1)
-            J[ndof + P, ndof + P] = W * (wgt * deq[P]).sum()
+            IP = Ir[P]  # [nd, nb]
+            J[rows, ndof + P] = (dphi[P][None, :] * (IP - eq[P][None, :])
+                                 - phi[P][None, :] * deq[P][None, :]).reshape(-1)
+            J[ndof + P, rows] = -np.outer(inst.w, wgt[P]).reshape(-1)
+            J[ndof + P, ndof + P] = (dwgt[P] * (W * eq[P] - e[P]) + wgt[P] * W * deq[P]).sum()
         r = np.concatenate([rI, rT])
         # row scaling for conditioning
         scale = np.abs(J).max(axis=1)

@@ -118,3 +118,38 @@ def test_null_context_calls_fail_cleanly():
     assert lib.bte_step(None, 1, None, None) == bte.BTE_E_INVAL
     assert lib.bte_temperature(None, T.ctypes.data_as(C.POINTER(C.c_double)), 4) == bte.BTE_E_INVAL
     assert lib.bte_destroy(None) == bte.BTE_OK
+
+
+def test_explicit_step_limit_without_device():
+    """Forward Euler is refused where dt (1/tau_b + sum_a v_b |s_a| / h_a) > 1
+    for some band and direction (the update would no longer be a convex
+    combination of old values); the message names the largest stable dt."""
+    base = inputs.config_c1()
+    rate = max(1.0 / base.tau[b] + sum(base.vg[b] * abs(base.s[d, a]) / base.h[a] for a in range(2))
+               for b in range(base.n_bands) for d in range(base.n_dirs))
+    rc, msg = _create_status(base, scheme=bte.BTE_EXPLICIT_EULER, dt=1.01 / rate)
+    assert rc == bte.BTE_E_INVAL and "explicit step too large" in msg
+    assert f"{1.0 / rate:.6g}" in msg
+    # the implicit scheme has no such limit (it fails later, at the fake workspace)
+    rc, msg = _create_status(base, scheme=bte.BTE_IMPLICIT_JACOBI, dt=1.01 / rate)
+    assert "explicit step" not in msg
+    rc, msg = _create_status(base, scheme=bte.BTE_EXPLICIT_EULER, dt=0.99 / rate)
+    assert "explicit step" not in msg
+
+
+def test_state_header_layout_matches_binding(tmp_path):
+    """The checkpoint header as the C compiler lays it out (include/bte.h) is
+    the one the binding parses."""
+    src = tmp_path / "hdr.c"
+    fields = [name for name, _ in bte.bte_state_header._fields_]
+    body = "".join(f'  printf("{f} %zu\\n", offsetof(bte_state_header, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "bte.h"\nint main(void) {\n'
+                   + body + '  printf("size %zu\\n", sizeof(bte_state_header));\n  return 0;\n}\n')
+    exe = tmp_path / "hdr"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    str(src)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for f in fields:
+        assert int(out[f]) == getattr(bte.bte_state_header, f).offset, f
+    assert int(out["size"]) == C.sizeof(bte.bte_state_header)

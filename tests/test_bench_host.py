@@ -49,3 +49,24 @@ def test_traffic_only_for_the_measured_source(tmp_path):
     assert bench.measured_traffic(str(src), str(tmp_path / "missing.json")) is None
     counters.write_text("not json")
     assert bench.measured_traffic(str(src), str(counters)) is None
+
+
+def test_sweep_bytes_of_the_explicit_paper_demo():
+    # forward Euler reads I^n once and writes I^{n+1}
+    inst = I.config_f1()
+    assert inst.n_dof == 120 * 120 * 20 * 55
+    assert bench.sweep_bytes(inst, 8) == inst.n_dof * 16 + 55 * 120 * 120 * 16
+
+
+def test_workload_defaults():
+    """Every single-geometry workload has a generator; c3 and c4 default to
+    FP32 storage (their configuration), c4's FP64 state does not fit one GPU,
+    and the paper context quotes the paper's ~18x with its hardware."""
+    for name, wl in bench.WORKLOADS.items():
+        inst = I.CONFIGS[name]()
+        assert wl["steps"] == inst.nsteps
+    assert bench.WORKLOADS["c3"]["precision"] == "fp32"
+    assert bench.WORKLOADS["c4"]["precision"] == "fp32" and not bench.WORKLOADS["c4"]["fp64_fits"]
+    pc = bench.PAPER_CONTEXT
+    assert pc["paper_speedup"] == 18.0 and "A6000" in pc["gpu"] and "Cascade Lake" in pc["cpu"]
+    assert pc["precision"] == "FP64"

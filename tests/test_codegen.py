@@ -69,4 +69,4 @@ def test_barriers_stay_in_uniform_loops(src, tmp_path):
             assert max(ds) == 0, f"{fn}: unexpected barrier inside a loop (depths {ds})"
     if src == "bte_kernels.hip":
         persistent = [fn for fn in depths if "batch_sweep_kernel" in fn]
-        assert len(persistent) == 6  # 3 work lists x 2 storage precisions
+        assert len(persistent) == 12  # 3 work lists x 2 storage precisions x stored or decoded items

@@ -264,3 +264,40 @@ def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
             ry, rz, ndg, ms = s3.autotune(None, batch=True)
             assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4), (0, 2), (0, 4)})
             assert ms > 0
+
+
+@pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
+def test_batch_matches_oracle(gpu, precision):
+    """Every geometry of a graph-replayed batch against the FP64 oracle, both
+    free-running to a tight tolerance (where any two correct solvers land on
+    the unique fixed point): FP64 within 1e-10, FP32 storage within 1e-5 in T
+    (sweep counts may differ by one near the tolerance)."""
+    import torch
+    from oracle import Oracle
+    tol = 1e-12 if precision == I.PRECISION_FP64 else 1e-10
+    insts = [inst.copy(tol=tol) for inst in geometries(precision)]
+    nsteps = 3
+    stream = torch.cuda.Stream()
+    announce(f"batch of {len(insts)} against the oracle, precision={precision}, tol={tol:g}")
+    sols = [gpu.Solver(inst, stream=stream) for inst in insts]
+    with gpu.Batch(sols, use_graph=True) as batch:
+        st = batch.step(nsteps)
+    worst_T, worst_I = 0.0, 0.0
+    for i, (inst, s) in enumerate(zip(insts, sols)):
+        ref = Oracle(inst)
+        ref_st = ref.run(nsteps)
+        T, Iq = s.temperature(), s.intensity()
+        s.close()
+        k_gpu = [st[k][i]["inner"] for k in range(nsteps)]
+        k_ref = [x["inner"] for x in ref_st]
+        errT = float(np.max(np.abs(T - ref.temperature()) / ref.temperature()))
+        I_ref = np.ascontiguousarray(ref.intensity().transpose(2, 1, 0))
+        errI = float(np.max(np.abs(Iq - I_ref) / np.abs(I_ref)))
+        print(f"geometry {i} {inst.name}: sweeps {k_gpu} oracle {k_ref}, T {errT:.2e} "
+              f"I {errI:.2e}", flush=True)
+        assert all(abs(a - b) <= 1 for a, b in zip(k_gpu, k_ref))
+        worst_T, worst_I = max(worst_T, errT), max(worst_I, errI)
+    if precision == I.PRECISION_FP64:
+        assert worst_T <= 1e-10 and worst_I <= 1e-10
+    else:
+        assert worst_T <= 1e-5 and worst_I <= 1e-4

@@ -212,7 +212,7 @@ def test_set_state_round_trip(gpu):
     announce("set_state round trip")
     with gpu.Solver(inst) as a, gpu.Solver(inst) as b:
         a.step(2)
-        b.set_state(a.intensity(), a.temperature())
+        b.set_fields(a.intensity(), a.temperature())
         sa = a.step(2)
         sb = b.step(2)
         assert [s["inner"] for s in sa] == [s["inner"] for s in sb]
@@ -233,7 +233,7 @@ def test_numeric_failure_names_cell(gpu):
         T = sol.temperature()
         bad = 123
         Iq[:, :, bad] = -1e12  # no positive energy can come out of this cell
-        sol.set_state(Iq, T)
+        sol.set_fields(Iq, T)
         with pytest.raises(gpu.BteError) as e:
             sol.step(1)
         assert e.value.code == gpu.BTE_E_NUMERIC
@@ -267,3 +267,21 @@ def test_sweep_timing_counts_sweeps(gpu):
         ms, n = sol.sweep_time()
     assert n == sum(s["inner"] for s in st)
     assert ms > 0.0
+
+
+# ---------------------------------------------------------------- the paper's own workload
+@pytest.mark.parametrize("n,steps", [(24, 30), (120, 20)])
+def test_paper_demo_explicit_parity(gpu, n, steps):
+    """The paper's demonstration scenario (Gaussian hot spot on one isothermal
+    wall, cold opposite wall, symmetry sides, 20 in-plane directions x 55
+    band entries, forward Euler at 1 ps, 4.375 um cells): a 24 x 24 cut of it
+    and the full 120 x 120 mesh, against the oracle."""
+    inst = I.paper_demo(n=n, length=n * 525e-6 / 120)
+    ref, ref_st, st, T, Iq = run_pair(gpu, inst, steps)
+    assert all(s["inner"] == 1 for s in st)
+    errT = rel(T, ref.temperature())
+    errI = rel(Iq, to_gpu_layout(ref.intensity()))
+    print(f"paper demo {n}x{n}, {steps} explicit steps: T {errT:.2e} I {errI:.2e}, max T "
+          f"{T.max():.6f}", flush=True)
+    assert errT <= 1e-10 and errI <= 1e-10
+    assert T.max() > 300.0 + 1e-6  # the hot spot has begun to heat the first row

@@ -516,3 +516,118 @@ def test_warm_step_reaches_the_same_fixed_point(maker, shift):
     assert rel(b.intensity(), a.intensity()) <= 1e-11
     with pytest.raises(OracleError):
         b.step_warm(-T0)
+
+
+def test_paper_demo_instance():
+    """The paper's demonstration workload as generated (Sec. 3.1 and its
+    schematic): counts, the Gaussian hot-spot profile at the face centres
+    (1/e^2 of the 50 K rise 10 um from the centre), wall kinds, and a forward
+    Euler step that keeps every update a convex combination."""
+    with open(os.path.join(GOLDEN, "paper_counts.json")) as f:
+        g = json.load(f)
+    f1 = I.config_f1()
+    assert f1.n[:2] == [120, 120] and abs(f1.h[0] * 120 - 525e-6) < 1e-18
+    assert f1.n_dirs * f1.n_bands == g["dof_per_cell_2d"]
+    assert abs(f1.n_dof - g["dof_total_2d"]) / g["dof_total_2d"] < 0.02
+    assert f1.scheme == I.SCHEME_EXPLICIT_EULER and f1.dt == 1e-12 and f1.nsteps == 100
+    assert f1.wall[:4] == [I.WALL_SYMMETRY, I.WALL_SYMMETRY, I.WALL_ISOTHERMAL, I.WALL_ISOTHERMAL]
+    assert np.all(f1.wall_T[2] == 300.0) and np.all(f1.T_init == 300.0)
+    x = (np.arange(120) + 0.5) * f1.h[0] - 262.5e-6
+    rise = f1.wall_T[3] - 300.0
+    # every heated face implies a 1/e^2 distance of 10 um for a 50 K peak
+    hot = rise > 1e-3
+    assert hot.sum() >= 6
+    dist = np.sqrt(2.0 * x[hot] ** 2 / np.log(50.0 / rise[hot]))
+    assert np.allclose(dist, 10e-6, rtol=1e-9)
+    assert np.allclose(rise, rise[::-1]) and rise.max() < 50.0 and rise.min() < 1e-12
+    assert np.allclose(np.abs(f1.s[:, 2]), 0.0, atol=1e-15)  # in-plane directions
+    rate = max(1.0 / f1.tau[b] + sum(f1.vg[b] * abs(f1.s[d, a]) / f1.h[a] for a in range(2))
+               for b in range(f1.n_bands) for d in range(f1.n_dirs))
+    assert f1.dt * rate <= 1.0
+
+
+# ---------------------------------------------------------------- temperature-dependent tau
+def with_tau_law(inst, seed=3, lo=0.5, hi=2.5):
+    """The same instance with tau_b(T) = tau_b (300 K / T)^p_b, p_b drawn
+    uniformly in [lo, hi] per band entry (scattering rates growing with T)."""
+    out = inst.copy()
+    out.tau_exp = np.random.default_rng(seed).uniform(lo, hi, inst.n_bands)
+    out.tau_T0 = 300.0
+    return out
+
+
+def test_tau_law_zero_exponents_is_constant_tau():
+    inst = tiny_2d(seed=19, n=(5, 4))
+    flat = inst.copy()
+    flat.tau_exp = np.zeros(inst.n_bands)
+    a, b = Oracle(inst), Oracle(flat)
+    for _ in range(3):
+        assert a.step() == b.step()
+    assert np.array_equal(a.intensity(), b.intensity())
+    assert np.array_equal(a.temperature(), b.temperature())
+
+
+@pytest.mark.parametrize("maker", [tiny_2d, tiny_3d, tiny_2d_aniso])
+def test_tau_law_step_matches_dense_newton(maker):
+    """With tau_b(T), the Jacobi step run to round-off equals the dense Newton
+    solution of the whole backward-Euler system in which every relaxation term
+    takes tau at its cell's temperature and T solves
+    sum_b (W I0_b(T) - e_b)/tau_b(T) = 0; and the law visibly changes the result."""
+    inst = with_tau_law(maker())
+    o = Oracle(inst)
+    const = Oracle(maker())
+    In, Tn = o.intensity(), o.temperature()
+    for _ in range(3):
+        o.step(fixed_inner=300)
+        const.step(fixed_inner=300)
+        Ib, Tb = brute.solve_backward_euler(inst, In, Tn, inst.dt)
+        assert rel(o.intensity(), Ib) < 1e-12
+        assert rel(o.temperature(), Tb) < 1e-12
+        In, Tn = Ib, Tb
+    assert rel(o.temperature(), const.temperature()) > 1e-6
+
+
+def test_tau_law_one_band_closed_form():
+    """One band: the factor 1/tau(T) cannot vanish, so the root is W I0(T) = e
+    whatever the law: T = hbar omega / (k_B ln(1 + W C / e))."""
+    inst = with_tau_law(tiny_2d(nb=1), lo=1.5, hi=1.5)
+    o = Oracle(inst)
+    W = inst.w.sum()
+    x_ref = brute.HBAR * inst.omega[0] / (brute.KB * 300.0)
+    Cb = o.equilibrium(0, 300.0) * math.expm1(x_ref)
+    for e_scale in (0.3, 1.0, 4.0):
+        e = e_scale * W * o.equilibrium(0, 300.0)
+        T_exact = brute.HBAR * inst.omega[0] / (brute.KB * math.log1p(W * Cb / e))
+        for T0 in (150.0, 300.0, 700.0):
+            T, it = o.invert_temperature_bands(np.array([e]), T0)
+            assert abs(T - T_exact) / T_exact < 1e-14
+
+
+@pytest.mark.parametrize("scheme", [I.SCHEME_IMPLICIT_JACOBI, I.SCHEME_EXPLICIT_EULER])
+def test_tau_law_uniform_state_bitwise_invariant(scheme):
+    inst = with_tau_law(tiny_2d(n=(5, 4), kinds=(0, 1, 0, 2)))
+    inst.T_init[:] = 310.0  # away from the law's reference temperature
+    for f in range(6):
+        if inst.wall_T[f] is not None:
+            inst.wall_T[f][:] = 310.0
+    o = Oracle(inst, scheme=scheme, dt=1e-13)
+    I0, T0 = o.intensity(), o.temperature()
+    for _ in range(4):
+        o.step()
+    assert np.array_equal(o.intensity(), I0) and np.array_equal(o.temperature(), T0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tau_law_adiabatic_box_conserves_energy(dim):
+    """Specular box: with the relaxation-time-weighted temperature taken with
+    the same tau_b(T) as the relaxation term, sum V E is conserved to
+    round-off; with the plain energy sum it is not (the planted mismatch)."""
+    inst = with_tau_law(adiabatic_box(dim=dim, n=(6, 5) if dim == 2 else (3, 4, 3)))
+    o = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=1e-13)
+    E0 = o.step()["energy"]
+    E = [o.step()["energy"] for _ in range(30)]
+    assert max(abs(e - E0) / E0 for e in E) < 1e-13
+    bad = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=1e-13, t_definition=I.TDEF_ENERGY)
+    E0 = bad.step()["energy"]
+    E = [bad.step()["energy"] for _ in range(30)]
+    assert max(abs(e - E0) / E0 for e in E) > 1e-9
