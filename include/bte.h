@@ -356,6 +356,21 @@ int bte_batch_create(int n, bte_ctx* const* ctxs, int use_graph, bte_batch** out
 int bte_batch_step(bte_batch* batch, int nsteps, bte_step_stats* stats);
 int bte_batch_destroy(bte_batch* batch);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the batched step of
+ * bte_batch_step without a batch object, allocating nothing.  Its geometry
+ * descriptors, work lists (kept as per-geometry item ranges) and counters
+ * live in a fixed device array of the library, one per GPU (219 KB,
+ * held until the process ends), filled afresh by every call; the host stages
+ * them in a fixed block under a lock, so calls from several threads take
+ * turns, and calls that overlap on one GPU through other means race.  Same
+ * rules as bte_batch_create for the contexts, plus: at most 256 contexts, and
+ * no context may still have to record or train its warm-start network (train
+ * it first by stepping it alone or in a bte_batch).  No graph is captured;
+ * the host waits for each inner iteration.  Results equal bte_batch_step's.
+ * stats (nullable): [nsteps][n]. */
+int bte_batch_step_static(int n, bte_ctx* const* ctxs, int nsteps, bte_step_stats* stats);
+
 /* Releases host-side resources (not the caller's workspace). */
 int bte_destroy(bte_ctx* ctx);
 

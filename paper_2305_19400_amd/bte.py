@@ -36,7 +36,8 @@ EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "b
            "bte_sweep_time", "bte_sweep_layout",
            "bte_nn_param_count", "bte_nn_params",
            "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_autotune",
-           "bte_batch_create", "bte_batch_step", "bte_batch_destroy", "bte_destroy",
+           "bte_batch_create", "bte_batch_step", "bte_batch_destroy", "bte_batch_step_static",
+           "bte_destroy",
            "bte_last_error")
 
 _dp = C.POINTER(C.c_double)
@@ -138,6 +139,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                      C.POINTER(C.c_void_p)]
     lib.bte_batch_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(bte_step_stats)]
     lib.bte_batch_destroy.argtypes = [C.c_void_p]
+    lib.bte_batch_step_static.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int,
+                                          C.POINTER(bte_step_stats)]
     lib.bte_last_error.restype = C.c_char_p
     for name in EXPORTS:
         getattr(lib, name).restype = C.c_char_p if name == "bte_last_error" else C.c_int
@@ -417,6 +420,17 @@ def parse_state(buf) -> dict:
 def _stats_dict(s) -> dict:
     return dict(inner=s.inner, converged=s.converged, newton_max=s.newton_max, res=s.res,
                 warm=s.warm, fallbacks=s.fallbacks, trained=s.trained, nn_loss=s.nn_loss)
+
+
+def batch_step_static(solvers, nsteps: int = 1):
+    """Steps several Solvers (sharing one stream) together through
+    bte_batch_step_static, which allocates nothing; returns stats[step][geometry]."""
+    lib = load_library()
+    n = len(solvers)
+    arr = (C.c_void_p * n)(*[s._ctx.value for s in solvers])
+    st = (bte_step_stats * max(1, nsteps * n))()
+    _check(lib.bte_batch_step_static(n, arr, int(nsteps), st))
+    return [[_stats_dict(st[k * n + i]) for i in range(n)] for k in range(nsteps)]
 
 
 class Batch:

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1975,6 +1976,167 @@ int bte_batch_destroy(bte_batch* b) {
   if (b->h_bc) (void)hipHostFree(b->h_bc);
   if (b->h_ctl) (void)hipHostFree(b->h_ctl);
   delete b;
+  return BTE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch step that allocates nothing
+// For callers that cannot allocate (graph capture, tight serving loops):
+// bte_batch_step_static runs the batched step of bte_batch_step without a
+// batch object.  The geometry descriptors, the work lists (kept as per-
+// geometry item ranges, decoded by the persistent sweeps) and the counters
+// live in the file-scope device array `scratch`, one copy per GPU; the host
+// side stages them in a file-scope host block under a mutex.  No graph is
+// captured (instantiating one allocates).
+namespace {
+
+constexpr int kStaticBatchMax = 256;  // contexts per call
+
+struct StaticBatch {
+  BatchCtx ctx[kStaticBatchMax];
+  BatchControl bc;
+  int list_ctx[kBatchLists][kStaticBatchMax];
+  int list_start[kBatchLists][kStaticBatchMax + 1];
+};
+
+// host staging: descriptors and lists on the way in, control words on the way out
+struct StaticBatchHost {
+  StaticBatch dev;  // mirror of the device block
+  Control ctl[kStaticBatchMax];
+  StepState ss[kStaticBatchMax];
+  int order[kStaticBatchMax];
+};
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[sizeof(StaticBatch)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;                       // guards the host staging and the table below
+StaticBatchHost g_static_host;                // file-scope: nothing allocated per call
+StaticBatch* g_static_dev[kMaxDevices] = {};  // device address of `scratch` on each GPU
+
+// The device address of `scratch` on the current GPU (looked up once per
+// GPU; the array's name is not a device address in host code).  Called with
+// g_static_mu held.
+int static_scratch(StaticBatch** out) {
+  int dev = 0;
+  bte_ctx* ctx = nullptr;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(BTE_E_DEVICE, "device %d out of range", dev);
+  if (!g_static_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_static_dev[dev] = static_cast<StaticBatch*>(p);
+  }
+  *out = g_static_dev[dev];
+  return BTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bte_batch_step_static(int n, bte_ctx* const* ctxs, int nsteps, bte_step_stats* stats) {
+  bte_ctx* ctx = nullptr;
+  if (n < 1 || !ctxs) return fail(BTE_E_INVAL, "need at least one context");
+  if (n > kStaticBatchMax)
+    return fail(BTE_E_INVAL, "at most %d contexts per call (got %d)", kStaticBatchMax, n);
+  if (nsteps < 0) return fail(BTE_E_INVAL, "nsteps must be >= 0");
+  {
+    const int rc = check_batch_members(n, ctxs);
+    if (rc != BTE_OK) return rc;
+  }
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i]->s.warm && !ctxs[i]->nn_ready)
+      return fail(BTE_E_INVAL,
+                  "context %d would record and train its warm-start network in these steps "
+                  "(training allocates): step it with bte_batch_step or alone until trained", i);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticBatch* d = nullptr;
+  {
+    const int rc = static_scratch(&d);
+    if (rc != BTE_OK) return rc;
+  }
+  StaticBatchHost& H = g_static_host;
+  const hipStream_t stream = ctxs[0]->stream;
+  const int precision = ctxs[0]->opt.precision;
+  // work lists, largest geometry first (as bte_batch_create orders them)
+  for (int i = 0; i < n; ++i) H.order[i] = i;
+  std::stable_sort(H.order, H.order + n, [&](int a, int c) {
+    const double wa = (double)ctxs[a]->s.nc * ctxs[a]->s.nd * ctxs[a]->s.nb;
+    const double wc = (double)ctxs[c]->s.nc * ctxs[c]->s.nd * ctxs[c]->s.nb;
+    return wa > wc;
+  });
+  int counts[kBatchLists] = {0, 0, 0};
+  int ngeo[kBatchLists] = {0, 0, 0};
+  int max_inner = 0;
+  for (int k = 0; k < n; ++k) {
+    const int i = H.order[k];
+    const SweepPlan& pl = ctxs[i]->s.plan;
+    const int l = batch_list_of(pl);
+    const long long items = (long long)pl.ndg * ctxs[i]->s.nb * pl.ntiles;
+    if ((long long)counts[l] + items > INT_MAX)
+      return fail(BTE_E_INVAL, "work list %d exceeds 2^31 items", l);
+    H.dev.list_ctx[l][ngeo[l]] = i;
+    H.dev.list_start[l][ngeo[l]] = counts[l];
+    ngeo[l] += 1;
+    counts[l] += (int)items;
+    max_inner = std::max(max_inner, ctxs[i]->opt.max_inner);
+  }
+  for (int l = 0; l < kBatchLists; ++l) H.dev.list_start[l][ngeo[l]] = counts[l];
+  BatchRanges ranges[kBatchLists];
+  for (int l = 0; l < kBatchLists; ++l)
+    ranges[l] = BatchRanges{ngeo[l], d->list_ctx[l], d->list_start[l]};
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  int sweep_blocks[kBatchLists];
+  for (int l = 0; l < kBatchLists; ++l) sweep_blocks[l] = cus * batch_sweep_occupancy(precision, l);
+  int temp_blocks = 0;
+  for (int i = 0; i < n; ++i)
+    temp_blocks += (ctxs[i]->s.nc + temp_cells_per_block(ctxs[i]->s.nb) - 1) /
+                   temp_cells_per_block(ctxs[i]->s.nb);
+  HIP_TRY(hipMemcpyAsync(d->list_ctx, H.dev.list_ctx, sizeof(H.dev.list_ctx),
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(d->list_start, H.dev.list_start, sizeof(H.dev.list_start),
+                         hipMemcpyHostToDevice, stream));
+  for (int step = 0; step < nsteps; ++step) {
+    int block0 = 0;
+    for (int i = 0; i < n; ++i) {
+      ctx = ctxs[i];
+      if (ctx->poisoned) return fail(BTE_E_DEVICE, "context %d is poisoned", i);
+      int rc = step_begin(ctx, 0, &H.ss[i]);
+      if (rc != BTE_OK) return rc;
+      fill_batch_ctx(H.dev.ctx[i], ctx, block0);
+      block0 += H.dev.ctx[i].cell_blocks;
+    }
+    ctx = nullptr;
+    HIP_TRY(hipMemcpyAsync(d->ctx, H.dev.ctx, sizeof(BatchCtx) * n, hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(launch_batch_reset(stream, d->ctx, n, &d->bc));
+    for (int j = 0; j < max_inner; ++j) {
+      HIP_TRY(launch_batch_iteration_ranges(stream, precision, d->ctx, n, ranges, counts, &d->bc,
+                                            sweep_blocks, temp_blocks));
+      HIP_TRY(hipMemcpyAsync(&H.dev.bc, &d->bc, sizeof(BatchControl), hipMemcpyDeviceToHost,
+                             stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (H.dev.bc.active == 0) break;
+    }
+    for (int i = 0; i < n; ++i)
+      HIP_TRY(hipMemcpyAsync(&H.ctl[i], ctxs[i]->ctl, sizeof(Control), hipMemcpyDeviceToHost,
+                             stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (int i = 0; i < n; ++i) {
+      const int rc = step_finish(ctxs[i], H.ss[i], H.ctl[i],
+                                 stats ? &stats[(size_t)step * n + i] : nullptr);
+      if (rc != BTE_OK) return rc;
+    }
+  }
   return BTE_OK;
 }
 
