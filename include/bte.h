@@ -56,8 +56,17 @@ enum bte_status {
 };
 
 /* Wall kinds (Eq. eq-bdry).  Specular and symmetry give the same ghost on
- * axis-aligned walls: the cell's own intensity in the mirrored direction. */
-enum bte_wall { BTE_WALL_ISOTHERMAL = 0, BTE_WALL_SPECULAR = 1, BTE_WALL_SYMMETRY = 2 };
+ * axis-aligned walls: the cell's own intensity in the mirrored direction.
+ * DIFFUSE (adiabatic, not among the paper's kinds): the wall re-emits the
+ * energy flux leaving the cell through it isotropically; the ghost of every
+ * inflow direction is sum_{s.n > 0} w_d (s.n) I_{d,b} / sum_{s.n > 0} w_d (s.n)
+ * of the cell at the current iterate. */
+enum bte_wall {
+  BTE_WALL_ISOTHERMAL = 0,
+  BTE_WALL_SPECULAR = 1,
+  BTE_WALL_SYMMETRY = 2,
+  BTE_WALL_DIFFUSE = 3
+};
 
 /* Time discretisation.  IMPLICIT_JACOBI: backward Euler, point-Jacobi inner
  * sweeps, temperature re-inverted after every sweep.  EXPLICIT_EULER: the
@@ -285,6 +294,13 @@ int bte_get_state(bte_ctx* ctx, void* buf, size_t bytes);
  * recording length or storage reference, or is truncated; the context is
  * then untouched. */
 int bte_set_state(bte_ctx* ctx, const void* buf, size_t bytes);
+
+/* New face temperatures of an isothermal wall (side 0..5, n = that side's
+ * face count, each > 0) for the steps that follow: the boundary of the paper's
+ * boundary callbacks that changes in time, set from the host between steps
+ * (Sec. 3.2, boundary conditions as callbacks).  BTE_E_INVAL if the side is
+ * not isothermal. */
+int bte_set_wall_temperature(bte_ctx* ctx, int side, const double* T_face, size_t n);
 
 /* Sum and count of the sweep-kernel durations measured since the last call
  * (options.timing must be set); resets the accumulators. */

@@ -26,6 +26,11 @@
  *     direction (specular / symmetry; identical on axis-aligned walls).
  */
 /*
+ *   - Diffuse walls (the paper's walls are isothermal or symmetric; a diffuse
+ *     adiabatic wall is the common third kind of phonon boundary): a wall face
+ *     re-emits the energy flux that leaves the cell through it, isotropically:
+ *     the ghost of every inflow direction is the outgoing flux-weighted mean
+ *     sum_{s.n > 0} w_d (s.n) I_{d,b} / sum_{s.n > 0} w_d (s.n) of the cell.
  *   - Relaxation times that depend on temperature (Sec. 2.2: I0 and tau both
  *     depend on T; the paper gives no law): tau_b(T) = tau_b (T0 / T)^p_b per
  *     band entry, i.e. a scattering rate growing as T^p_b.  The sweep takes
@@ -336,6 +341,8 @@ oracle_bte* oracle_create(int dim, const int* n, const double* h, const int* wal
         for (int b = 0; b < nb; ++b)
           o->wall_I0[side][(size_t)f * nb + b] = oracle_equilibrium(o, b, wall_T[side][f]);
       }
+    } else if (kind == ORACLE_WALL_DIFFUSE) {
+      /* nothing to precompute: the ghost follows the cell's own intensity */
     } else if (kind == ORACLE_WALL_SPECULAR || kind == ORACLE_WALL_SYMMETRY) {
       int axis = side / 2;
       for (int d = 0; d < nd; ++d)
@@ -410,6 +417,18 @@ static double balance(const oracle_bte* o, const double* I, int P, int x, int y,
       if (!on_wall) {
         int Q = P + ((f % 2) ? stride[axis] : -stride[axis]);
         Iin = I[idx(o, Q, d, b)];
+      } else if (o->wall[f] == ORACLE_WALL_DIFFUSE) {
+        /* re-emission of the outgoing flux through this face (outward normal
+           component of direction d' along axis: sd'[axis] * normal > 0) */
+        double num = 0.0, den = 0.0;
+        for (int e = 0; e < o->nd; ++e) {
+          double mu_e = o->s[3 * e + axis] * normal;
+          if (mu_e > 0.0) {
+            num += o->w[e] * mu_e * I[idx(o, P, e, b)];
+            den += o->w[e] * mu_e;
+          }
+        }
+        Iin = num / den;
       } else if (o->wall[f] == ORACLE_WALL_ISOTHERMAL) {
         int fi = wall_face_index(o, f, x, y, z);
         Iin = o->wall_I0[f][(size_t)fi * o->nb + b];
@@ -598,6 +617,18 @@ int oracle_set_state(oracle_bte* o, const double* I, const double* T) {
   memcpy(o->In, I, sizeof(double) * (size_t)o->nc * o->nd * o->nb);
   memcpy(o->Tn, T, sizeof(double) * o->nc);
   memcpy(o->Tprev, T, sizeof(double) * o->nc);
+  return ORACLE_OK;
+}
+
+int oracle_set_wall_temperature(oracle_bte* o, int side, const double* T_face) {
+  if (side < 0 || side >= 2 * o->dim || o->wall[side] != ORACLE_WALL_ISOTHERMAL || !T_face)
+    return ORACLE_E_INVAL;
+  int nf = o->nc / o->n[side / 2];
+  for (int f = 0; f < nf; ++f)
+    if (!(T_face[f] > 0.0)) return ORACLE_E_INVAL;
+  for (int f = 0; f < nf; ++f)
+    for (int b = 0; b < o->nb; ++b)
+      o->wall_I0[side][(size_t)f * o->nb + b] = oracle_equilibrium(o, b, T_face[f]);
   return ORACLE_OK;
 }
 

@@ -38,6 +38,7 @@ extern "C" {
 #define ORACLE_WALL_ISOTHERMAL 0
 #define ORACLE_WALL_SPECULAR 1
 #define ORACLE_WALL_SYMMETRY 2
+#define ORACLE_WALL_DIFFUSE 3 /* adiabatic, re-emits the outgoing flux isotropically */
 
 #define ORACLE_IMPLICIT 0
 #define ORACLE_EXPLICIT 1
@@ -88,6 +89,8 @@ void oracle_get_I(const oracle_bte* o, double* I);          /* [N_c][N_d][N_b] *
 void oracle_get_E(const oracle_bte* o, double* E, double* G); /* [N_c] each, may be NULL */
 int oracle_set_state(oracle_bte* o, const double* I, const double* T);
 int oracle_failed_cell(const oracle_bte* o);                /* last numeric failure, -1 if none */
+/* New face temperatures [faces] of an isothermal wall, for the next steps. */
+int oracle_set_wall_temperature(oracle_bte* o, int side, const double* T_face);
 void oracle_set_threads(int n);
 int oracle_get_threads(void);
 

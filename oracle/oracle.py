@@ -70,6 +70,7 @@ def _load():
     lib.oracle_get_E.argtypes = [C.c_void_p, _dp, _dp]
     lib.oracle_set_state.argtypes = [C.c_void_p, _dp, _dp]
     lib.oracle_failed_cell.argtypes = [C.c_void_p]
+    lib.oracle_set_wall_temperature.argtypes = [C.c_void_p, C.c_int, _dp]
     lib.oracle_set_threads.argtypes = [C.c_int]
     lib.oracle_get_threads.restype = C.c_int
     lib.oracle_equilibrium.restype = C.c_double
@@ -192,6 +193,12 @@ class Oracle:
             raise OracleError("state size mismatch")
         if self.lib.oracle_set_state(self._h, _ptr(I), _ptr(T)) != 0:
             raise OracleError("bad state")
+
+    def set_wall_temperature(self, side: int, T_face):
+        """New face temperatures of an isothermal wall for the next steps."""
+        T_face = np.ascontiguousarray(T_face, dtype=np.float64)
+        if self.lib.oracle_set_wall_temperature(self._h, int(side), _ptr(T_face)) != 0:
+            raise OracleError("bad wall temperature")
 
     def equilibrium(self, b: int, T: float) -> float:
         return float(self.lib.oracle_equilibrium(self._h, int(b), float(T)))

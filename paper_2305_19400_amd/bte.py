@@ -24,7 +24,7 @@ BTE_E_NUMERIC = -4
 BTE_E_NOTCONV = -5
 BTE_E_STATE = -6
 
-BTE_WALL_ISOTHERMAL, BTE_WALL_SPECULAR, BTE_WALL_SYMMETRY = 0, 1, 2
+BTE_WALL_ISOTHERMAL, BTE_WALL_SPECULAR, BTE_WALL_SYMMETRY, BTE_WALL_DIFFUSE = 0, 1, 2, 3
 BTE_IMPLICIT_JACOBI, BTE_EXPLICIT_EULER = 0, 1
 BTE_FP64, BTE_FP32_MIXED = 0, 1
 BTE_T_TAU_WEIGHTED, BTE_T_ENERGY = 0, 1
@@ -33,7 +33,7 @@ BTE_WARM_NONE, BTE_WARM_T, BTE_WARM_T_SHIFT = 0, 1, 2
 # every symbol include/bte.h declares
 EXPORTS = ("bte_workspace_size", "bte_create", "bte_step", "bte_temperature", "bte_intensity",
            "bte_energy", "bte_set_fields", "bte_state_size", "bte_get_state", "bte_set_state",
-           "bte_sweep_time", "bte_sweep_layout",
+           "bte_set_wall_temperature", "bte_sweep_time", "bte_sweep_layout",
            "bte_nn_param_count", "bte_nn_params",
            "bte_nn_set_params", "bte_nn_predict", "bte_nn_gradient", "bte_autotune",
            "bte_batch_create", "bte_batch_step", "bte_batch_destroy", "bte_batch_step_static",
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.bte_state_size.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
     lib.bte_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     lib.bte_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.bte_set_wall_temperature.argtypes = [C.c_void_p, C.c_int, _dp, C.c_size_t]
     lib.bte_sweep_time.argtypes = [C.c_void_p, _dp, _ip]
     lib.bte_sweep_layout.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip]
     _fp = C.POINTER(C.c_float)
@@ -288,6 +289,12 @@ class Solver:
         T = _f64(T).reshape(-1)
         _check(self.lib.bte_set_fields(self._ctx, I.ctypes.data_as(_dp), I.size,
                                        T.ctypes.data_as(_dp), T.size))
+
+    def set_wall_temperature(self, side: int, T_face):
+        """New face temperatures of an isothermal wall for the next steps."""
+        T = _f64(T_face).reshape(-1)
+        _check(self.lib.bte_set_wall_temperature(self._ctx, int(side), T.ctypes.data_as(_dp),
+                                                 T.size))
 
     def get_state(self) -> bytearray:
         """Checkpoint of everything the next steps depend on (bte_get_state)."""

@@ -47,7 +47,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t ctl, coef, dflags, mirror, w, Cb, xfac, inv_tau, fweight, Iref;
-  size_t wallT[6], wallI0[6], wallS[6];
+  size_t wallT[6], wallI0[6], wallS[6], dwt;
   size_t T, Tprev, E, I0, S, part, relax, tau_p;
   // learned warm start (present if warm_start != 0)
   size_t nn_params, nn_grad, nn_m, nn_v, nn_W1b, nn_W2b, nn_W2Tb, nn_y, nn_hist, nn_loss,
@@ -59,7 +59,8 @@ struct Layout {
 struct Shape {
   int dim, nx, ny, nz, nc, ncp, nd, nb;
   int nf[6];
-  bool iso[6];
+  bool iso[6];   // isothermal: face temperatures given
+  bool diff[6];  // diffuse: ghost table recomputed every iteration
   size_t real_size;
   SweepPlan plan;
   int ndg_cap, nparts_cap;  // room for any layout the autotuner may pick
@@ -101,10 +102,12 @@ Layout make_layout(const Shape& s) {
   L.fweight = take(sizeof(double) * (size_t)s.nb);
   L.Iref = take(sizeof(double) * (size_t)s.nb);
   for (int f = 0; f < 6; ++f) {
+    const bool table = s.iso[f] || s.diff[f];
     L.wallT[f] = s.iso[f] ? take(sizeof(double) * (size_t)s.nf[f]) : 0;
-    L.wallI0[f] = s.iso[f] ? take(sizeof(double) * (size_t)s.nf[f] * s.nb) : 0;
-    L.wallS[f] = s.iso[f] ? take(s.real_size * (size_t)s.nf[f] * s.nb) : 0;
+    L.wallI0[f] = table ? take(sizeof(double) * (size_t)s.nf[f] * s.nb) : 0;
+    L.wallS[f] = table ? take(s.real_size * (size_t)s.nf[f] * s.nb) : 0;
   }
+  L.dwt = take(sizeof(double) * 6 * (size_t)s.nd);
   L.T = take(sizeof(double) * (size_t)s.ncp);
   L.Tprev = take(sizeof(double) * (size_t)s.ncp);
   L.E = take(sizeof(double) * (size_t)s.ncp);
@@ -259,11 +262,14 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   for (int f = 0; f < 6; ++f) {
     s.nf[f] = nfaces[f / 2];
     s.iso[f] = false;
+    s.diff[f] = false;
     if (f >= 2 * s.dim) continue;
     const int kind = m->wall[f];
     if (kind == BTE_WALL_ISOTHERMAL) {
       if (!m->wall_T[f]) return fail(BTE_E_INVAL, "isothermal wall %d needs wall_T", f);
       s.iso[f] = true;
+    } else if (kind == BTE_WALL_DIFFUSE) {
+      s.diff[f] = true;
     } else if (kind != BTE_WALL_SPECULAR && kind != BTE_WALL_SYMMETRY) {
       return fail(BTE_E_INVAL, "unknown wall kind %d on side %d", kind, f);
     }
@@ -331,6 +337,8 @@ struct bte_ctx {
   bool nn_loss_pending = false;     // trained; loss not read yet
   int nn_last_batch = 1;            // samples of the last minibatch
   long long steps_taken = 0;        // time steps completed since create
+  double* dwt = nullptr;            // [6][nd] diffuse walls' outgoing-flux weights
+  bool any_diffuse = false;
   bool poisoned;
 };
 
@@ -393,6 +401,24 @@ int enqueue_iteration(bte_ctx* ctx, int j, int fixed_k) {
     HIP_TRY(hipEventRecord(ctx->t_start[j], ctx->stream));
   }
   const double* shift = (j == 0) ? ctx->first_shift : nullptr;
+  if (ctx->any_diffuse) {
+    // diffuse walls' ghosts from the iterate this sweep reads
+    for (int f = 0; f < 2 * ctx->s.dim; ++f) {
+      if (!ctx->s.diff[f]) continue;
+      double* w0 = const_cast<double*>(ctx->t.wall_I0[f]);
+      void* wsr = const_cast<void*>(ctx->t.wall_S[f]);
+      if (ctx->opt.precision == BTE_FP64)
+        HIP_TRY(launch_diffuse_wall<double>(ctx->stream, ctx->g, ctx->t, f,
+                                            ctx->dwt + (size_t)f * ctx->s.nd,
+                                            static_cast<const double*>(src), shift, w0,
+                                            static_cast<double*>(wsr)));
+      else
+        HIP_TRY(launch_diffuse_wall<float>(ctx->stream, ctx->g, ctx->t, f,
+                                           ctx->dwt + (size_t)f * ctx->s.nd,
+                                           static_cast<const float*>(src), shift, w0,
+                                           static_cast<float*>(wsr)));
+    }
+  }
   int rc = ctx->opt.precision == BTE_FP64 ? enqueue_sweep<double>(ctx, src, dst, shift)
                                           : enqueue_sweep<float>(ctx, src, dst, shift);
   if (rc != BTE_OK) return rc;
@@ -805,7 +831,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   std::vector<int> mirror;
   find_mirrors(dirs, s.dim, mirror);
   for (int f = 0; f < 2 * s.dim; ++f) {
-    if (s.iso[f]) continue;
+    if (s.iso[f] || s.diff[f]) continue;
     const int a = f / 2;
     for (int i = 0; i < nd; ++i)
       if (mirror[(size_t)a * nd + i] < 0)
@@ -942,11 +968,17 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   t.explicit_scheme = opt->scheme == BTE_EXPLICIT_EULER;
   t.W = W;
   for (int f = 0; f < 6; ++f) {
-    t.wall[f] = (f < 2 * s.dim) ? mesh->wall[f] : BTE_WALL_SPECULAR;
+    // the sweeps read a diffuse wall's ghosts from its table, as an isothermal one's
+    t.wall[f] = (f < 2 * s.dim) ? (s.diff[f] ? (int)BTE_WALL_ISOTHERMAL : mesh->wall[f])
+                                : BTE_WALL_SPECULAR;
     t.wall_nf[f] = s.nf[f];
-    t.wall_I0[f] = s.iso[f] ? at<double>(ws, L.wallI0[f]) : nullptr;
-    t.wall_S[f] = s.iso[f] ? static_cast<const void*>(ws + L.wallS[f]) : nullptr;
+    const bool table = s.iso[f] || s.diff[f];
+    t.wall_I0[f] = table ? at<double>(ws, L.wallI0[f]) : nullptr;
+    t.wall_S[f] = table ? static_cast<const void*>(ws + L.wallS[f]) : nullptr;
   }
+  ctx->dwt = at<double>(ws, L.dwt);
+  ctx->any_diffuse = false;
+  for (int f = 0; f < 6; ++f) ctx->any_diffuse |= s.diff[f];
 
   auto cleanup_fail = [&](int code) {
     bte_destroy(ctx);
@@ -978,6 +1010,30 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
     std::vector<double> tau_p(nb, 0.0);
     if (disp->tau_exp) tau_p.assign(disp->tau_exp, disp->tau_exp + nb);
     CREATE_TRY(up(L.tau_p, tau_p.data(), sizeof(double) * nb));
+    CREATE_TRY(hipStreamSynchronize(ctx->stream));  // the vector goes out of scope
+  }
+  {
+    // per side: normalised outgoing-flux weights w_d (s_d . n) of the
+    // directions leaving through it (zero for the others)
+    std::vector<double> dwt(6 * (size_t)nd, 0.0);
+    for (int f = 0; f < 2 * s.dim; ++f) {
+      if (!s.diff[f]) continue;
+      const double n_out = (f % 2) ? 1.0 : -1.0;
+      double sum = 0.0;
+      for (int i = 0; i < nd; ++i) {
+        const double mu = dirs->s[3 * (size_t)i + f / 2] * n_out;
+        if (mu > 0.0) {
+          dwt[(size_t)f * nd + i] = dirs->w[i] * mu;
+          sum += dwt[(size_t)f * nd + i];
+        }
+      }
+      if (!(sum > 0.0)) {
+        fail(BTE_E_INVAL, "no direction leaves through diffuse wall %d", f);
+        return cleanup_fail(BTE_E_INVAL);
+      }
+      for (int i = 0; i < nd; ++i) dwt[(size_t)f * nd + i] /= sum;
+    }
+    CREATE_TRY(up(L.dwt, dwt.data(), sizeof(double) * dwt.size()));
     CREATE_TRY(hipStreamSynchronize(ctx->stream));  // the vector goes out of scope
   }
   CREATE_TRY(up(L.T, mesh->T_init, sizeof(double) * s.nc));
@@ -1434,6 +1490,32 @@ int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const
   return BTE_OK;
 }
 
+int bte_set_wall_temperature(bte_ctx* ctx, int side, const double* T_face, size_t n) {
+  if (!ctx) return fail(BTE_E_INVAL, "null context");
+  if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
+  if (side < 0 || side >= 2 * ctx->s.dim || !ctx->s.iso[side])
+    return fail(BTE_E_INVAL, "side %d is not an isothermal wall", side);
+  if (!T_face || n != (size_t)ctx->s.nf[side])
+    return fail(BTE_E_INVAL, "side %d has %d faces, got %zu temperatures", side,
+                ctx->s.nf[side], n);
+  for (size_t i = 0; i < n; ++i)
+    if (!(T_face[i] > 0.0) || !std::isfinite(T_face[i]))
+      return fail(BTE_E_INVAL, "wall %d face %zu temperature must be positive", side, i);
+  const Layout& L = ctx->L;
+  double* wT = at<double>(ctx->ws, L.wallT[side]);
+  double* w0 = at<double>(ctx->ws, L.wallI0[side]);
+  HIP_TRY(hipMemcpyAsync(wT, T_face, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(launch_wall_table(ctx->stream, ctx->s.nb, (int)n, ctx->t.Cb, ctx->t.xfac, wT, w0));
+  if (ctx->opt.precision == BTE_FP64)
+    HIP_TRY(launch_wall_storage<double>(ctx->stream, ctx->s.nb, (int)n, w0, ctx->t.Iref,
+                                        at<double>(ctx->ws, L.wallS[side])));
+  else
+    HIP_TRY(launch_wall_storage<float>(ctx->stream, ctx->s.nb, (int)n, w0, ctx->t.Iref,
+                                       at<float>(ctx->ws, L.wallS[side])));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BTE_OK;
+}
+
 int bte_sweep_time(bte_ctx* ctx, double* total_ms, int* count) {
   if (!ctx) return fail(BTE_E_INVAL, "null context");
   if (total_ms) *total_ms = ctx->timing_ms;
@@ -1690,6 +1772,9 @@ int check_batch_members(int n, bte_ctx* const* ctxs) {
                   "batches need the 4-row 2D, the 2x2 or 1x4 3D column-walk or the "
                   "flattened-plane layout (context %d)", i);
     if (c->opt.timing) return fail(BTE_E_INVAL, "per-sweep timing is not available in batches");
+    if (c->any_diffuse)
+      return fail(BTE_E_INVAL, "batches take isothermal, specular and symmetry walls "
+                  "(context %d has a diffuse wall)", i);
     if (c->t.relax)
       return fail(BTE_E_INVAL,
                   "batches take constant relaxation times (context %d has a temperature law)", i);

@@ -238,6 +238,15 @@ template <typename Real>
 hipError_t launch_wall_storage(hipStream_t stream, int nb, int nf, const double* in,
                                const double* Iref, Real* out);
 
+// The ghost table of a diffuse wall side from the current iterate I:
+// wall_I0[b][face] = sum_d wts[d] I_{d,b,P(face)} (+ the isotropic first-sweep
+// shift of P, if given), wts the side's normalised outgoing-flux weights, and
+// wall_S the same in storage format.
+template <typename Real>
+hipError_t launch_diffuse_wall(hipStream_t stream, const Geometry& g, const Tables& t, int side,
+                               const double* wts, const Real* I, const double* shift,
+                               double* wall_I0, Real* wall_S);
+
 // Iref[b] = I0_b(T_ref) if T_ref > 0, else 0.
 hipError_t launch_reference(hipStream_t stream, int nb, const double* Cb, const double* xfac,
                             double T_ref, double* Iref);

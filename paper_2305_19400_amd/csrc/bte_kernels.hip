@@ -1680,6 +1680,63 @@ hipError_t launch_equilibrium(hipStream_t stream, const Geometry& g, const Table
   return hipGetLastError();
 }
 
+// Diffuse wall: per (face, band), the outgoing flux-weighted mean of the wall
+// cell's intensities at the current iterate, as a ghost table in FP64 and in
+// storage format (the sweeps read it like an isothermal wall's).  FP32
+// storage sums the deviations, so the reference is added once.
+template <typename Real>
+__global__ void diffuse_wall_kernel(Geometry g, Tables t, int side, const double* __restrict__ wts,
+                                    const Real* __restrict__ I, const double* __restrict__ shift,
+                                    double* __restrict__ wall_I0, Real* __restrict__ wall_S) {
+  const int nf = t.wall_nf[side];
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (f >= nf) return;
+  const int axis = side / 2, plus = side % 2;
+  int x, y, z;
+  if (axis == 0) {
+    x = plus ? g.nx - 1 : 0;
+    y = f % g.ny;
+    z = f / g.ny;
+  } else if (axis == 1) {
+    y = plus ? g.ny - 1 : 0;
+    x = f % g.nx;
+    z = f / g.nx;
+  } else {
+    z = plus ? g.nz - 1 : 0;
+    x = f % g.nx;
+    y = f / g.nx;
+  }
+  const size_t P = (size_t)x + (size_t)g.nx * (y + (size_t)g.ny * z);
+  const size_t ncp = (size_t)g.ncp;
+  const double ref = Storage<Real>::kDeviation ? t.Iref[b] : 0.0;
+  double dev = 0.0;
+  for (int d = 0; d < g.nd; ++d) {
+    const double wd = wts[d];
+    if (wd > 0.0) dev += wd * static_cast<double>(I[((size_t)b * g.nd + d) * ncp + P]);
+  }
+  if (shift) dev += shift[(size_t)b * ncp + P];
+  wall_I0[(size_t)b * nf + f] = ref + dev;
+  wall_S[(size_t)b * nf + f] = Storage<Real>::kDeviation ? static_cast<Real>(dev)
+                                                         : static_cast<Real>(ref + dev);
+}
+
+template <typename Real>
+hipError_t launch_diffuse_wall(hipStream_t stream, const Geometry& g, const Tables& t, int side,
+                               const double* wts, const Real* I, const double* shift,
+                               double* wall_I0, Real* wall_S) {
+  const dim3 grid((t.wall_nf[side] + 63) / 64, g.nb);
+  hipLaunchKernelGGL((diffuse_wall_kernel<Real>), grid, dim3(64), 0, stream, g, t, side, wts, I,
+                     shift, wall_I0, wall_S);
+  return hipGetLastError();
+}
+template hipError_t launch_diffuse_wall<double>(hipStream_t, const Geometry&, const Tables&, int,
+                                                const double*, const double*, const double*,
+                                                double*, double*);
+template hipError_t launch_diffuse_wall<float>(hipStream_t, const Geometry&, const Tables&, int,
+                                               const double*, const float*, const double*,
+                                               double*, float*);
+
 // Equilibrium intensity of every face of an isothermal wall, [b][face].
 __global__ void wall_table_kernel(int nb, int nf, const double* __restrict__ Cb,
                                   const double* __restrict__ xfac,

@@ -33,6 +33,7 @@ import numpy as np
 WALL_ISOTHERMAL = 0
 WALL_SPECULAR = 1
 WALL_SYMMETRY = 2
+WALL_DIFFUSE = 3
 
 SCHEME_IMPLICIT_JACOBI = 0
 SCHEME_EXPLICIT_EULER = 1

@@ -60,7 +60,8 @@ def assemble(inst, dt):
     h = np.array(inst.h, dtype=float)
     if dim == 2:
         h[2] = 1.0
-    mirrors = [_mirror(s, a) for a in range(3)]
+    mirrors = [_mirror(s, a) if any(inst.wall[f] in (1, 2) for f in (2 * a, 2 * a + 1)
+                                    if f < 2 * dim) else None for a in range(3)]
     ndof = nc * nd * nb
 
     def lin(P, d, b):
@@ -94,6 +95,14 @@ def assemble(inst, dt):
                             other = [a for a in range(3) if a != axis]
                             fi = c[other[0]] + inst.n[other[0]] * c[other[1]]
                             src[i] -= coef * wall_I0[f][fi, b]
+                        elif inst.wall[f] == 3:
+                            # diffuse: the outgoing flux-weighted mean of the cell
+                            mu_out = s[:, axis] * n_out
+                            out = mu_out > 0
+                            wts = inst.w * np.where(out, mu_out, 0.0)
+                            wts = wts / wts.sum()
+                            for e in np.nonzero(out)[0]:
+                                L[i, lin(P, e, b)] += coef * wts[e]
                         else:
                             L[i, lin(P, mirrors[axis][d], b)] += coef
     return L, src

@@ -631,3 +631,92 @@ def test_tau_law_adiabatic_box_conserves_energy(dim):
     E0 = bad.step()["energy"]
     E = [bad.step()["energy"] for _ in range(30)]
     assert max(abs(e - E0) / E0 for e in E) > 1e-9
+
+
+# ---------------------------------------------------------------- diffuse walls, wall updates
+def diffuse_2d():
+    return tiny_2d(seed=24, n=(4, 3), kinds=(3, 0, 1, 3))
+
+
+def diffuse_3d():
+    return tiny_3d(seed=25, kinds=(3, 0, 2, 3, 0, 3))
+
+
+@pytest.mark.parametrize("maker", [diffuse_2d, diffuse_3d])
+def test_diffuse_step_matches_dense_newton(maker):
+    """Diffuse walls: the Jacobi step run to round-off equals the dense Newton
+    solution of the whole backward-Euler system whose inflow rows at a
+    diffuse face carry the outgoing flux-weighted mean of the cell's
+    intensities (assembled as matrix entries)."""
+    inst = maker()
+    o = Oracle(inst)
+    In, Tn = o.intensity(), o.temperature()
+    for _ in range(3):
+        o.step(fixed_inner=300)
+        Ib, Tb = brute.solve_backward_euler(inst, In, Tn, inst.dt)
+        assert rel(o.intensity(), Ib) < 1e-12
+        assert rel(o.temperature(), Tb) < 1e-12
+        In, Tn = Ib, Tb
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_diffuse_box_conserves_energy(dim):
+    """A box with every wall diffuse: each wall returns the flux that reaches it
+    (the quadrature's inflow and outflow weights w |s.n| balance), so sum V E
+    is conserved to round-off in explicit mode."""
+    inst = adiabatic_box(dim=dim, n=(6, 5) if dim == 2 else (3, 4, 3))
+    inst.wall = [3] * (2 * dim) + [0] * (6 - 2 * dim)
+    o = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=1e-13)
+    E0 = o.step()["energy"]
+    E = [o.step()["energy"] for _ in range(30)]
+    assert max(abs(e - E0) / E0 for e in E) < 1e-13
+    T = o.temperature()
+    assert T.max() - T.min() < inst.T_init.max() - inst.T_init.min()
+
+
+def test_diffuse_equals_specular_with_one_direction_per_side():
+    """With two in-plane directions (phi = 90 and 270 degrees) a y wall has a
+    single outgoing and a single incoming direction, so re-emitting the
+    outgoing flux isotropically returns the mirrored intensity: diffuse and
+    specular y walls give the same steps."""
+    base = tiny_2d(seed=26, n=(3, 5), nphi=2, kinds=(0, 0, 1, 1))
+    diff = base.copy(wall=[0, 0, 3, 3, 0, 0])
+    a, b = Oracle(base), Oracle(diff)
+    for _ in range(3):
+        a.step(fixed_inner=6)
+        b.step(fixed_inner=6)
+    assert rel(b.temperature(), a.temperature()) < 1e-14
+    assert rel(b.intensity(), a.intensity()) < 1e-14
+
+
+def test_diffuse_uniform_state_invariant():
+    inst = tiny_2d(n=(5, 4), kinds=(3, 0, 3, 0))
+    inst.T_init[:] = 300.0
+    for f in range(6):
+        if inst.wall_T[f] is not None:
+            inst.wall_T[f][:] = 300.0
+    o = Oracle(inst)
+    I0, T0 = o.intensity(), o.temperature()
+    for _ in range(3):
+        o.step()
+    assert rel(o.intensity(), I0) < 1e-14 and rel(o.temperature(), T0) < 1e-14
+
+
+def test_set_wall_temperature_is_a_new_boundary():
+    """Changing an isothermal wall's face temperatures between steps gives the
+    steps of a context created with the new wall from the same state."""
+    inst = tiny_2d(seed=27, n=(5, 4), kinds=(0, 1, 0, 2))
+    hot = inst.copy()
+    hot.wall_T[0] = inst.wall_T[0] + np.linspace(5.0, 15.0, inst.wall_T[0].size)
+    a = Oracle(inst)
+    a.run(2)
+    I_mid, T_mid = a.intensity(), a.temperature()
+    a.set_wall_temperature(0, hot.wall_T[0])
+    a.run(2)
+    b = Oracle(hot)
+    b.set_state(I_mid, T_mid)
+    b.run(2)
+    assert np.array_equal(a.intensity(), b.intensity())
+    assert np.array_equal(a.temperature(), b.temperature())
+    with pytest.raises(OracleError):
+        a.set_wall_temperature(1, hot.wall_T[0])  # side 1 is specular
