@@ -77,9 +77,7 @@ enum bte_scheme { BTE_IMPLICIT_JACOBI = 0, BTE_EXPLICIT_EULER = 1 };
 /* Storage / arithmetic of the intensity sweep.  FP32_MIXED stores each
  * intensity as its FP32 deviation from I0_b at the coldest input temperature; the
  * sweep computes the update in FP64 and rounds it once to storage, and the
- * energy reduction, temperature inversion and residual norms are FP64.
- * With EXPLICIT_EULER, FP32_MIXED always sweeps one cell per thread (the
- * layout overrides and bte_autotune leave it so). */
+ * energy reduction, temperature inversion and residual norms are FP64. */
 enum bte_precision { BTE_FP64 = 0, BTE_FP32_MIXED = 1 };
 
 /* Temperature definition.  TAU_WEIGHTED: W sum_b I0_b(T)/tau_b =

@@ -211,12 +211,6 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   // with FP64 storage and 1 row x 4 planes with FP32 storage (the faster at
   // 64^3).
   const bool fp32 = o->precision != BTE_FP64;
-  // The tiled kernels evaluate the FP32-storage update in the direct form
-  // (I^n/dt + I0/tau + sum c I_up) * scale, which is the implicit Jacobi
-  // update only; forward Euler also needs -(1/tau + sum c) I^n.  The
-  // cell-per-thread kernel forms the increment of I^k for either scheme, so
-  // FP32 storage with the explicit scheme always takes it (no overrides).
-  const bool cell_only = fp32 && o->scheme == BTE_EXPLICIT_EULER;
   int ry_dflt = 0, rz_dflt = 0, kind_dflt = -1;
   if (s.dim == 3) {
     const double lanes_used = (double)s.nx / (64.0 * ((s.nx + 63) / 64));
@@ -232,8 +226,7 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   }
   s.plan = make_sweep_plan(s.dim, s.nx, s.ny, s.nz, s.nd, s.nb, env_int("BTE_SWEEP_RY", ry_dflt),
                            env_int("BTE_SWEEP_RZ", rz_dflt), env_int("BTE_SWEEP_NDG", 0),
-                           cell_only ? (int)kSweepCellPerThread
-                                     : env_int("BTE_SWEEP_KIND", kind_dflt));
+                           env_int("BTE_SWEEP_KIND", kind_dflt));
   s.ndg_cap = s.plan.ndg;
   s.nparts_cap = s.plan.nparts;
   if (s.plan.kind == kSweepColumnWalk2D) {
@@ -870,6 +863,9 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
         diag += cf.c[a];
       }
       cf.scale = opt->scheme == BTE_EXPLICIT_EULER ? opt->dt : 1.0 / diag;
+      cf.q = opt->scheme == BTE_EXPLICIT_EULER
+                 ? 1.0 / opt->dt - (((inv_tau[b] + cf.c[0]) + cf.c[1]) + cf.c[2])
+                 : 1.0 / opt->dt;
       const double rate = inv_tau[b] + cf.c[0] + cf.c[1] + cf.c[2];
       if (rate > max_rate) {
         max_rate = rate;

@@ -44,11 +44,16 @@ struct Control {
 
 // Per (band, direction) sweep coefficients: c[a] = v_b |s_{d,a}| / h_a and the
 // update scale (1 / diagonal for Jacobi, dt for forward Euler).
+// Per (band, direction): c_a = v_b |s_{d,a}| / h_a; scale = 1 / (1/dt + 1/tau_b +
+// sum_a c_a) (backward Euler) or dt (forward Euler); q = the coefficient of
+// I^n in the direct form of the FP32-storage update: 1/dt, or
+// 1/dt - 1/tau_b - sum_a c_a under forward Euler.
 struct Coef {
   double c[3];
   double scale;
+  double q;
 };
-static_assert(sizeof(Coef) == 4 * sizeof(double), "Coef is read as four contiguous doubles");
+static_assert(sizeof(Coef) == 5 * sizeof(double), "Coef is read as five contiguous doubles");
 
 // Direction flags: bit a set if s_{d,a} > 0, bit (4 + a) set if s_{d,a} < 0.
 __host__ __device__ inline bool dir_pos(int flags, int a) { return (flags >> a) & 1; }

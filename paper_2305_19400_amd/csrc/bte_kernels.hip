@@ -130,14 +130,17 @@ __device__ __forceinline__ double energy_partial(double S, double Sc, double ire
 // R = (I^n - I)/dt + (I0 - I)/tau + sum_in c (I_up - I) and a = 1/dt + 1/tau +
 // sum c.  With FP64 storage it is evaluated in this defect form, which leaves
 // a uniform equilibrium state bit for bit unchanged.  With FP32 storage the
-// equal direct form I_new = (I^n/dt + I0/tau + sum_in c I_up) / a is used on
-// the deviations (fewer operations); its FP64 rounding is far below the single
-// rounding to the stored value.  Each helper is one expression, so FMA
-// contraction is the same wherever it is inlined.
+// equal direct form I_new = (q I^n + I0/tau + sum_in c I_up) / a with q = 1/dt
+// is used on the deviations (fewer operations); its FP64 rounding is far
+// below the single rounding to the stored value.  Under forward Euler the
+// sweep reads I = I^n and 1/a = dt, and the same direct form is the explicit
+// update with q = 1/dt - 1/tau - sum_in c (the defect form needs no q).  Each
+// helper is one expression, so FMA contraction is the same wherever it is
+// inlined.
 template <typename Real, typename A>
-__device__ __forceinline__ A update_start(A in, A i0, A v, A inv_dt, A inv_tau) {
+__device__ __forceinline__ A update_start(A in, A i0, A v, A q, A inv_dt, A inv_tau) {
 #pragma clang fp contract(on)
-  if constexpr (Storage<Real>::kDeviation) return in * inv_dt + i0 * inv_tau;
+  if constexpr (Storage<Real>::kDeviation) return in * q + i0 * inv_tau;
   else return (in - v) * inv_dt + (i0 - v) * inv_tau;
 }
 template <typename Real, typename A>
@@ -199,12 +202,13 @@ __device__ __forceinline__ T cld(const T* base, size_t i) {
   return ((const __attribute__((address_space(4))) T*)base)[i];
 }
 __device__ __forceinline__ Coef cld_coef(const Coef* base, size_t i) {
-  const double* c = base[i].c;  // c[0], c[1], c[2], scale are contiguous doubles
+  const double* c = base[i].c;  // c[0], c[1], c[2], scale, q are contiguous doubles
   Coef r;
   r.c[0] = cld(c, 0);
   r.c[1] = cld(c, 1);
   r.c[2] = cld(c, 2);
   r.scale = cld(c, 3);
+  r.q = cld(c, 4);
   return r;
 }
 
@@ -471,6 +475,9 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     }
   }
   const A a_inv_dt = static_cast<A>(p.inv_dt), a_inv_tau = static_cast<A>(inv_tau);
+  // 1 under forward Euler, where the table's q holds the band's constant
+  // rate, which a temperature-dependent one replaces
+  const A a_expl = p.t.explicit_scheme ? A(1) : A(0);
   double num = 0.0, den = 0.0, wsum = 0.0;
 
   // Tile edges.  Lane j fetches the x-inflow value of row y0 + j (the
@@ -584,7 +591,9 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
       const A exj = read_lane(ex, j);
       if (colok && j < nrows) {
         const A v = ik[j];
-        A acc = update_start<Real>(in[j], I0r[j], v, a_inv_dt, TAUT ? rate[j] : a_inv_tau);
+        const A rt = TAUT ? rate[j] : a_inv_tau;
+        const A q = TAUT ? static_cast<A>(cf.q) + a_expl * (a_inv_tau - rt) : static_cast<A>(cf.q);
+        A acc = update_start<Real>(in[j], I0r[j], v, q, a_inv_dt, rt);
         if (xpos) {
           const A up = lane == 0 ? exj : nbr;
           acc = update_add<Real>(acc, c0, up, v);
@@ -735,6 +744,9 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
       }
   }
   const A a_inv_dt = static_cast<A>(p.inv_dt), a_inv_tau = static_cast<A>(inv_tau);
+  // 1 under forward Euler, where the table's q holds the band's constant
+  // rate, which a temperature-dependent one replaces
+  const A a_expl = p.t.explicit_scheme ? A(1) : A(0);
   // Block faces.  x: lane l fetches the x-inflow value of register row
   // (l % RY, l / RY); y: one value per plane; z: one value per row.
   const int jl = min(lane % RY, max(nrows - 1, 0));
@@ -885,8 +897,10 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
         const A exjk = read_lane(ex, j + RY * k);
         if (colok && j < nrows && k < nplanes) {
           const A v = ik[j][k];
-          A acc = update_start<Real>(in[j][k], I0r[j][k], v, a_inv_dt,
-                                     TAUT ? rate[j][k] : a_inv_tau);
+          const A rt = TAUT ? rate[j][k] : a_inv_tau;
+          const A q =
+              TAUT ? static_cast<A>(cf.q) + a_expl * (a_inv_tau - rt) : static_cast<A>(cf.q);
+          A acc = update_start<Real>(in[j][k], I0r[j][k], v, q, a_inv_dt, rt);
           if (xpos) {
             const A up = lane == 0 ? exjk : nbr;
             acc = update_add<Real>(acc, c0, up, v);
@@ -971,22 +985,31 @@ __global__ __launch_bounds__(kSweepBlock) void sweep3d_walk_kernel(const SweepPa
 
 // ---------------------------------------------------------------- 3D flattened walk
 // For meshes whose x extent leaves many lanes of a 64-column tile idle (a
-// narrow mesh, or a ragged last tile), the lanes of a wave take 64
-// consecutive cells f = x + nx y of the (x, y) plane instead, and the wave
-// holds RZ planes of them in registers; a workgroup covers 256 cells x RZ
-// planes.  The z-upwind neighbour comes from registers (one load per block
-// face plane), the x-upwind one from the adjacent lane (the wave's edge lane
-// from one load per plane), the y-upwind one from a load of the cells nx
-// away, which this or the previous wave has just read.  Lanes on an x or y
-// wall take the ghost (isothermal equilibrium in storage format, or the
-// cell's own intensity in the mirrored direction) from a load masked to them.
+// narrow mesh, or a ragged last tile), the 256 lanes of a workgroup take 256
+// consecutive cells f = x + nx y of the (x, y) plane instead, and each lane
+// holds RZ planes of its cell in registers.  The z-upwind neighbour comes from
+// registers (one load per block face plane).  For the x- and y-upwind
+// neighbours the workgroup stages its tile's source values in LDS for every
+// direction (two buffers alternating by direction, one barrier per
+// direction): a neighbour inside the tile is read from there, and only the
+// tile's halo (the row before its first or after its last cell, and the cell
+// beyond either end) is loaded from memory.  Without the staging every wave
+// loaded the rows and edge cells that its neighbour waves load at the same
+// time, and those duplicate requests went out to memory as well.  Lanes on an
+// x or y wall take the ghost (isothermal equilibrium in storage format, or
+// the cell's own intensity in the mirrored direction) from a load masked to
+// them.
 template <typename Real, int RZ, bool SHIFT, bool TAUT>
 __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const int nft,
                                             const int dgs, const int bx, const int by,
                                             const int bz, const int gx, const int gy) {
 #pragma clang fp contract(on)  // fuse a*b+c only within one expression
   using A = Arith<Real>;
+  // staged values carry the cell's shift when there is one
+  using L = std::conditional_t<SHIFT, A, Real>;
   constexpr int sz = (int)sizeof(Real);
+  constexpr int kTile = kSweepBlock;
+  __shared__ L stage[2][RZ][kTile];
   const Geometry& g = p.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int nxy = nx * ny;
@@ -994,17 +1017,20 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
   const int tz = bx / nft;
   const int b = by;
   const int dg = bz;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int f0 = tf * 256 + wave * 64;   // first plane cell of this wave
-  const int f = f0 + lane;
+  const int li = threadIdx.x;            // the cell's place in the plane tile
+  const int wave = __builtin_amdgcn_readfirstlane(li >> 6);
+  const int t0 = tf * kTile;             // first plane cell of the tile
+  const int f = t0 + li;
   const bool fok = f < nxy;
   const int fc = fok ? f : nxy - 1;      // a valid cell for every lane
   const int x = fc % nx;
   const int y = fc / nx;
   const int z0 = tz * RZ;
   const int nplanes = max(0, min(RZ, nz - z0));
-  const bool live = f0 < nxy && nplanes > 0;
+  // the whole workgroup runs the direction loop (it holds the barriers);
+  // waves whose cells all lie past the plane skip loads and updates
+  const bool block_live = t0 < nxy && nplanes > 0;
+  const bool live = t0 + wave * 64 < nxy && nplanes > 0;
   const int d_begin = dg * dgs;
   const int d_end = min(g.nd, d_begin + dgs);
   const size_t ncp = (size_t)g.ncp;
@@ -1022,13 +1048,17 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
     zp[k] = min(z0 + min(k, max(nplanes - 1, 0)), nz - 1);
     vc[k] = (zp[k] * nxy + fc) * sz;
   }
-  // neighbour cells in the plane (clamped to the cell itself on a wall)
+  // neighbour cells in the plane (clamped to the cell itself on a wall), and
+  // whether they lie in this tile
   const int fy_p = y > 0 ? fc - nx : fc;
   const int fy_n = y < ny - 1 ? fc + nx : fc;
-  // the wave's x edge: lane k loads plane k's cell before f0 / after f0 + 63
-  const int kl = min(lane, RZ - 1);
-  const int fe_p = max(f0 - 1, 0);
-  const int fe_n = min(f0 + 64, nxy - 1);
+  const bool yin_p = fy_p >= t0;
+  const bool yin_n = fy_n < t0 + kTile;
+  // the tile's x ends: lane 0 takes the cell before the tile, lane 255 the
+  // cell after it (the other lanes' value is never used)
+  const int fe = li == 0 ? max(t0 - 1, 0) : min(t0 + kTile, nxy - 1);
+  const bool xin_p = li > 0;
+  const bool xin_n = li < kTile - 1;
   // z block faces
   const bool wall_zp = z0 == 0;
   const bool wall_zn = z0 + nplanes >= nz;
@@ -1037,8 +1067,8 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
 
   A I0r[RZ], sh[RZ], rate[RZ];
   double S[RZ], Sc[RZ];
-  A shy_p[RZ], shy_n[RZ];
-  A shx_p = 0, shx_n = 0, shz_p = 0, shz_n = 0;
+  A shy_p[RZ], shy_n[RZ], shx[RZ];
+  A shz_p = 0, shz_n = 0;
   {
     const auto r0 = slab_rsrc(p.I0 + (size_t)b * ncp, g.nc * 8);
 #pragma unroll
@@ -1053,6 +1083,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
       sh[k] = 0;
       shy_p[k] = 0;
       shy_n[k] = 0;
+      shx[k] = 0;
     }
   }
   if constexpr (SHIFT) {
@@ -1062,110 +1093,148 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
       sh[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fc]);
       shy_p[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fy_p]);
       shy_n[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fy_n]);
+      shx[k] = static_cast<A>(sb[(size_t)zp[k] * nxy + fe]);
     }
-    shx_p = static_cast<A>(sb[(size_t)zp[kl] * nxy + fe_p]);
-    shx_n = static_cast<A>(sb[(size_t)zp[kl] * nxy + fe_n]);
     shz_p = static_cast<A>(sb[(size_t)pl_p * nxy + fc]);
     shz_n = static_cast<A>(sb[(size_t)pl_n * nxy + fc]);
   }
   const A a_inv_dt = static_cast<A>(p.inv_dt), a_inv_tau = static_cast<A>(inv_tau);
+  // 1 under forward Euler, where the table's q holds the band's constant
+  // rate, which a temperature-dependent one replaces
+  const A a_expl = p.t.explicit_scheme ? A(1) : A(0);
   double num = 0.0, den = 0.0, wsum = 0.0;
 
-  for (int d = d_begin; d < d_end && live; ++d) {
+  for (int d = d_begin; d < d_end && block_live; ++d) {
     const Coef cf = cld_coef(p.t.coef, (size_t)b * g.nd + d);
     const int fl = cld(p.t.dflags, (size_t)d);
     const double wd = cld(p.t.w, (size_t)d);
     const bool xpos = dir_pos(fl, 0), xneg = dir_neg(fl, 0);
     const bool ypos = dir_pos(fl, 1), yneg = dir_neg(fl, 1);
     const bool zpos = dir_pos(fl, 2), zneg = dir_neg(fl, 2);
-    const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
-    const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
-    const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
-    Real rk_v[RZ], rn_v[RZ], ey_r[RZ];
-    const int fy = ypos ? fy_p : fy_n;
-#pragma unroll
-    for (int k = 0; k < RZ; ++k) {
-      rk_v[k] = buf_load_raw<Real>(rk, vc[k]);
-      rn_v[k] = buf_load_raw<Real>(rn, vc[k]);
-      ey_r[k] = buf_load_raw<Real>(rk, (zp[k] * nxy + fy) * sz);
-    }
-    const Real ex_r = buf_load_raw<Real>(rk, (zp[kl] * nxy + (xpos ? fe_p : fe_n)) * sz);
-    // z face: the neighbouring block's plane, or on a wall (wave-uniform) the
-    // isothermal equilibrium or this plane's cell in the mirrored direction
-    const bool wz = zpos ? wall_zp : wall_zn;
-    const int fz = zpos ? 4 : 5;
-    const bool isoz = wz && p.t.wall[fz] == 0;
-    const int dzs = (wz && !isoz) ? cld(p.t.mirror, (size_t)2 * g.nd + d) : d;
-    const auto rzs = isoz ? slab_rsrc(p.t.wall_S[fz], g.nb * p.t.wall_nf[fz] * sz)
-                          : slab_rsrc(Ikb + (size_t)dzs * ncp, slab_bytes);
-    const Real ez_r = buf_load_raw<Real>(
-        rzs, isoz ? (b * p.t.wall_nf[fz] + fc) * sz
-                  : ((zpos ? pl_p : pl_n) * nxy + fc) * sz);
-    // x and y walls: lanes on a wall load their ghosts (masked to them)
     const bool xw = (xpos && x == 0) || (xneg && x == nx - 1);
     const bool yw = (ypos && y == 0) || (yneg && y == ny - 1);
-    A xg[RZ], yg[RZ];
-#pragma unroll
-    for (int k = 0; k < RZ; ++k) xg[k] = yg[k] = 0;
-    if (xw) {
-      const int fx = xpos ? 0 : 1;
-      const bool iso = p.t.wall[fx] == 0;
-      const auto r = iso ? slab_rsrc(p.t.wall_S[fx], g.nb * p.t.wall_nf[fx] * sz)
-                         : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)d) * ncp, slab_bytes);
-#pragma unroll
-      for (int k = 0; k < RZ; ++k)
-        xg[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fx] + y + ny * zp[k]) * sz : vc[k]);
-      if constexpr (SHIFT)
-        if (!iso)
-#pragma unroll
-          for (int k = 0; k < RZ; ++k) xg[k] += sh[k];
-    }
-    if (yw) {
-      const int fyw = ypos ? 2 : 3;
-      const bool iso = p.t.wall[fyw] == 0;
-      const auto r = iso ? slab_rsrc(p.t.wall_S[fyw], g.nb * p.t.wall_nf[fyw] * sz)
-                         : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)g.nd + d) * ncp,
-                                     slab_bytes);
-#pragma unroll
-      for (int k = 0; k < RZ; ++k)
-        yg[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fyw] + x + nx * zp[k]) * sz : vc[k]);
-      if constexpr (SHIFT)
-        if (!iso)
-#pragma unroll
-          for (int k = 0; k < RZ; ++k) yg[k] += sh[k];
-    }
-    A ex = ex_r, ez = ez_r;
-    if constexpr (SHIFT) {
-      ex += xpos ? shx_p : shx_n;
-      if (!isoz) ez += zpos ? shz_p : shz_n;
-    }
-    A ik[RZ], in[RZ];
+    const bool xin = xpos ? xin_p : xin_n;
+    const bool yin = ypos ? yin_p : yin_n;
+    const int fy = ypos ? fy_p : fy_n;
+    L (&st)[RZ][kTile] = stage[d & 1];
+    Real rk_v[RZ], rn_v[RZ], ey_r[RZ], ex_r[RZ];
+    A xg[RZ], yg[RZ], ik[RZ], in[RZ];
+    Real ez_r = 0;
+    bool isoz = false;
 #pragma unroll
     for (int k = 0; k < RZ; ++k) {
-      ik[k] = rk_v[k];
-      in[k] = rn_v[k];
-      if constexpr (SHIFT) ik[k] += sh[k];
+      ey_r[k] = ex_r[k] = 0;
+      xg[k] = yg[k] = 0;
     }
+    if (live) {
+      const auto rk = slab_rsrc(Ikb + (size_t)d * ncp, slab_bytes);
+      const auto rn = slab_rsrc(Inb + (size_t)d * ncp, slab_bytes);
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        rk_v[k] = buf_load_raw<Real>(rk, vc[k]);
+        rn_v[k] = buf_load_raw<Real>(rn, vc[k]);
+      }
+      // the halo: upwind cells outside the tile (masked to the lanes that
+      // need them)
+      if ((xpos || xneg) && !xin && !xw)
+#pragma unroll
+        for (int k = 0; k < RZ; ++k) ex_r[k] = buf_load_raw<Real>(rk, (zp[k] * nxy + fe) * sz);
+      if ((ypos || yneg) && !yin && !yw)
+#pragma unroll
+        for (int k = 0; k < RZ; ++k) ey_r[k] = buf_load_raw<Real>(rk, (zp[k] * nxy + fy) * sz);
+      // z face: the neighbouring block's plane, or on a wall (wave-uniform)
+      // the isothermal equilibrium or this plane's cell in the mirrored
+      // direction
+      const bool wz = zpos ? wall_zp : wall_zn;
+      const int fz = zpos ? 4 : 5;
+      isoz = wz && p.t.wall[fz] == 0;
+      const int dzs = (wz && !isoz) ? cld(p.t.mirror, (size_t)2 * g.nd + d) : d;
+      const auto rzs = isoz ? slab_rsrc(p.t.wall_S[fz], g.nb * p.t.wall_nf[fz] * sz)
+                            : slab_rsrc(Ikb + (size_t)dzs * ncp, slab_bytes);
+      ez_r = buf_load_raw<Real>(rzs, isoz ? (b * p.t.wall_nf[fz] + fc) * sz
+                                          : ((zpos ? pl_p : pl_n) * nxy + fc) * sz);
+      // x and y walls: lanes on a wall load their ghosts (masked to them)
+      if (xw) {
+        const int fx = xpos ? 0 : 1;
+        const bool iso = p.t.wall[fx] == 0;
+        const auto r = iso ? slab_rsrc(p.t.wall_S[fx], g.nb * p.t.wall_nf[fx] * sz)
+                           : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)d) * ncp, slab_bytes);
+#pragma unroll
+        for (int k = 0; k < RZ; ++k)
+          xg[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fx] + y + ny * zp[k]) * sz : vc[k]);
+        if constexpr (SHIFT)
+          if (!iso)
+#pragma unroll
+            for (int k = 0; k < RZ; ++k) xg[k] += sh[k];
+      }
+      if (yw) {
+        const int fyw = ypos ? 2 : 3;
+        const bool iso = p.t.wall[fyw] == 0;
+        const auto r = iso ? slab_rsrc(p.t.wall_S[fyw], g.nb * p.t.wall_nf[fyw] * sz)
+                           : slab_rsrc(Ikb + (size_t)cld(p.t.mirror, (size_t)g.nd + d) * ncp,
+                                       slab_bytes);
+#pragma unroll
+        for (int k = 0; k < RZ; ++k)
+          yg[k] = buf_load_raw<Real>(r, iso ? (b * p.t.wall_nf[fyw] + x + nx * zp[k]) * sz : vc[k]);
+        if constexpr (SHIFT)
+          if (!iso)
+#pragma unroll
+            for (int k = 0; k < RZ; ++k) yg[k] += sh[k];
+      }
+#pragma unroll
+      for (int k = 0; k < RZ; ++k) {
+        ik[k] = rk_v[k];
+        in[k] = rn_v[k];
+        if constexpr (SHIFT) ik[k] += sh[k];
+        if constexpr (SHIFT) st[k][li] = ik[k];
+        else st[k][li] = rk_v[k];
+      }
+    }
+    // the buffer written here was last read two directions ago, before every
+    // wave passed the previous direction's barrier.  The marker names this
+    // barrier in the assembly, where a static check allows it (alone) one
+    // loop level deeper than the kernel's other barriers.
+    asm volatile("; bte: direction-loop barrier" ::: "memory");
+    __syncthreads();
+    if (!live) continue;
+    A ez = ez_r;
+    if constexpr (SHIFT)
+      if (!isoz) ez += zpos ? shz_p : shz_n;
     const A c0 = static_cast<A>(cf.c[0]), c1 = static_cast<A>(cf.c[1]);
     const A c2 = static_cast<A>(cf.c[2]), scale = static_cast<A>(cf.scale);
     wsum += wd;
-    const int src_lane = xpos ? max(lane - 1, 0) : min(lane + 1, 63);
-    const int edge_lane = xpos ? 0 : 63;
+    const int lx = xpos ? li - 1 : li + 1;
+    const int ly = fy - t0;
+    const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
 #pragma unroll
     for (int k = 0; k < RZ; ++k) {
-      const A nbr = __shfl(ik[k], src_lane, 64);
-      const A exk = read_lane(ex, k);
-      A ey = ey_r[k];
-      if constexpr (SHIFT) ey += ypos ? shy_p[k] : shy_n[k];
       if (fok && k < nplanes) {
         const A v = ik[k];
-        A acc = update_start<Real>(in[k], I0r[k], v, a_inv_dt, TAUT ? rate[k] : a_inv_tau);
+        const A rt = TAUT ? rate[k] : a_inv_tau;
+        const A q = TAUT ? static_cast<A>(cf.q) + a_expl * (a_inv_tau - rt) : static_cast<A>(cf.q);
+        A acc = update_start<Real>(in[k], I0r[k], v, q, a_inv_dt, rt);
         if (xpos || xneg) {
-          const A up = xw ? xg[k] : (lane == edge_lane ? exk : nbr);
+          A up;
+          if (xw) {
+            up = xg[k];
+          } else if (xin) {
+            up = static_cast<A>(st[k][lx]);
+          } else {
+            up = ex_r[k];
+            if constexpr (SHIFT) up += shx[k];
+          }
           acc = update_add<Real>(acc, c0, up, v);
         }
         if (ypos || yneg) {
-          const A up = yw ? yg[k] : ey;
+          A up;
+          if (yw) {
+            up = yg[k];
+          } else if (yin) {
+            up = static_cast<A>(st[k][ly]);
+          } else {
+            up = ey_r[k];
+            if constexpr (SHIFT) up += ypos ? shy_p[k] : shy_n[k];
+          }
           acc = update_add<Real>(acc, c1, up, v);
         }
         if (zpos) {
@@ -1195,6 +1264,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
       p.S[((size_t)dg * g.nb + b) * ncp + vc[k] / sz] =
           energy_partial<Real>(S[k], Sc[k], iref, wsum);
 
+  const int lane = li & 63;
   __shared__ double red[2][kSweepBlock / 64];
   num = wave_sum(num);
   den = wave_sum(den);

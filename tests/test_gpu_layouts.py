@@ -78,12 +78,23 @@ def case_3d_narrow():
     return mixed_walls(inst, 56)
 
 
-CASES = {"2d": case_2d, "2dn": case_2d_narrow, "3d": case_3d, "3dn": case_3d_narrow}
+def case_3d_wide():
+    # rows longer than the flattened plane's 256-cell tile: every y-upwind
+    # cell lies in the tile's halo, and tile ends fall inside rows
+    inst = I.gaussian_3d(300, 3, 5, 2, 8, 3, seed=60, precision=I.PRECISION_FP64, nsteps=2)
+    inst.h = [0.9e-8, 1.1e-8, 1e-8]
+    inst.name = "layouts3d_300x3x5"
+    return mixed_walls(inst, 61)
+
+
+CASES = {"2d": case_2d, "2dn": case_2d_narrow, "3d": case_3d, "3dn": case_3d_narrow,
+         "3dw": case_3d_wide}
 KIND_WALK, KIND_FLAT = 1, 3  # kernel families (ry = 0: flattened (x, y) plane, 3D)
 LAYOUTS = [("2d", 4, 0, 1), ("2d", 8, 0, 3), ("2d", 16, 0, 2),
            ("2dn", 4, 0, 2), ("2dn", 8, 0, 1),
            ("3d", 2, 2, 1), ("3d", 1, 4, 2), ("3d", 2, 4, 3), ("3d", 0, 4, 1), ("3d", 0, 2, 2),
-           ("3dn", 2, 2, 1), ("3dn", 1, 4, 3), ("3dn", 0, 4, 2), ("3dn", 0, 2, 1)]
+           ("3dn", 2, 2, 1), ("3dn", 1, 4, 3), ("3dn", 0, 4, 2), ("3dn", 0, 2, 1),
+           ("3dw", 0, 4, 1), ("3dw", 0, 2, 2)]
 
 
 def set_layout(monkeypatch, ry, rz, ndg):
@@ -115,7 +126,7 @@ def test_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
 
 @pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 16, 0, 2), ("3d", 2, 2, 1), ("3d", 1, 4, 2),
                                              ("3d", 2, 4, 3), ("3d", 0, 4, 1), ("3d", 0, 2, 2),
-                                             ("3dn", 1, 4, 1)])
+                                             ("3dn", 1, 4, 1), ("3dw", 0, 4, 2)])
 def test_explicit_layout_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     """Forward-Euler steps (one sweep each, the update scaled by dt instead of
     the implicit diagonal) through every sweep family and layout."""
@@ -179,25 +190,34 @@ def test_degenerate_mesh_matches_oracle(gpu, monkeypatch, dim, n, layout):
     assert float(np.max(np.abs(T - inst.T_init))) > 1e-3
 
 
-@pytest.mark.parametrize("dim,layout", [("2d", None), ("3d", None), ("3dn", None),
-                                        ("2d", (8, 0, 3)), ("3d", (1, 4, 2)), ("3d", (0, 4, 1))])
+@pytest.mark.parametrize("dim,layout", [("2d", None), ("3d", None), ("3dn", None), ("3dw", None),
+                                        ("2d", (8, 0, 3)), ("3d", (1, 4, 2)), ("3d", (0, 4, 1)),
+                                        ("3dn", (2, 2, 2)), ("2d", "cell"), ("3dn", "cell")])
 def test_fp32_explicit_matches_oracle(gpu, monkeypatch, dim, layout):
-    """FP32 storage with forward-Euler steps sweeps one cell per thread
-    whatever layout is requested (the tiled kernels' FP32 update is the
-    implicit one), and matches the FP64 oracle to the FP32 bar."""
+    """FP32 storage with forward-Euler steps, through every kernel family: the
+    tiled kernels take the defect form of the update there (the direct form
+    they use under backward Euler lacks the -(1/tau + sum c) I^n term), and
+    every layout matches the FP64 oracle to the FP32 bar."""
     from oracle import Oracle
     inst = CASES[dim]()
     dt = 2e-13
-    if layout is not None:
+    if layout == "cell":
+        monkeypatch.setenv("BTE_SWEEP_KIND", "0")
+    elif layout is not None:
         set_layout(monkeypatch, *layout)
     ref = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=dt)
     ref.run(4)
-    announce(f"{inst.name} fp32 explicit, requested layout {layout}")
+    announce(f"{inst.name} fp32 explicit, layout {layout}")
     with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED, scheme=I.SCHEME_EXPLICIT_EULER,
                     dt=dt) as sol:
-        assert sol.sweep_layout()["kind"] == 0
-        assert sol.autotune()[:3] == (1, 1, 1)  # nothing to tune: the layout stays
-        assert sol.sweep_layout()["kind"] == 0
+        lay = sol.sweep_layout()
+        if layout == "cell":
+            assert lay["kind"] == 0
+        elif layout is not None:
+            kind = 1 if dim.startswith("2d") else (KIND_FLAT if layout[0] == 0 else 2)
+            assert lay == dict(kind=kind, ry=layout[0], rz=max(layout[1], 1), ndg=layout[2])
+        else:
+            assert lay["kind"] != 0
         st = sol.step(4)
         T, Iq = sol.temperature(), sol.intensity()
     assert all(s["inner"] == 1 for s in st)
@@ -209,8 +229,29 @@ def test_fp32_explicit_matches_oracle(gpu, monkeypatch, dim, layout):
     assert float(np.max(np.abs(T - inst.T_init))) > 1e-3
 
 
+def test_fp32_explicit_autotunes(gpu):
+    """FP32 storage with forward Euler is no longer tied to one kernel family:
+    the autotuner searches the 3D layouts and the tuned layout still matches
+    the oracle."""
+    from oracle import Oracle
+    inst = CASES["3dn"]()
+    dt = 2e-13
+    ref = Oracle(inst, scheme=I.SCHEME_EXPLICIT_EULER, dt=dt)
+    ref.run(2)
+    announce(f"{inst.name} fp32 explicit autotune")
+    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED, scheme=I.SCHEME_EXPLICIT_EULER,
+                    dt=dt) as sol:
+        ry, rz, ndg, ms = sol.autotune()
+        assert ms > 0 and sol.sweep_layout()["kind"] in (2, KIND_FLAT)
+        sol.step(2)
+        T = sol.temperature()
+    errT = float(np.max(np.abs(T - ref.temperature()) / ref.temperature()))
+    print(f"tuned ({ry}, {rz}, {ndg}): T {errT:.2e}", flush=True)
+    assert errT <= 1e-5
+
+
 @pytest.mark.parametrize("dim,ry,rz,ndg", [("2d", 8, 0, 3), ("2dn", 4, 0, 1), ("3d", 1, 4, 2),
-                                             ("3d", 0, 4, 1), ("3dn", 0, 2, 2)])
+                                             ("3d", 0, 4, 1), ("3dn", 0, 2, 2), ("3dw", 0, 4, 1)])
 def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     from oracle import Oracle
     inst = CASES[dim]()
@@ -226,7 +267,7 @@ def test_layout_fp32_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg):
     assert errT <= 1e-5
 
 
-@pytest.mark.parametrize("dim", ["3d", "3dn"])
+@pytest.mark.parametrize("dim", ["3d", "3dn", "3dw"])
 def test_warm_start_shift_is_layout_independent(gpu, monkeypatch, dim):
     """The first sweep of a warm-started step adds the equilibrium shift at the
     guessed temperature to every inflow value (neighbour, edge, mirrored

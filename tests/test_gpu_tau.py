@@ -6,7 +6,8 @@ temperature solves sum_b (W I0_b(T) - e_b) / tau_b(T) = 0.
 
 Every kernel family and layout (2D and 3D column walks, the flattened plane,
 one cell per thread), implicit and explicit, FP64 within 1e-10 with the
-oracle's sweep schedule replayed and FP32 storage within 1e-5 in T; the
+oracle's sweep schedule replayed and FP32 storage within 1e-5 in T (both
+schemes); the
 uniform state stays bitwise unchanged; a specular box conserves energy to
 round-off in explicit mode (only if the inversion and the relaxation term use
 the same tau_b(T)); a checkpoint resumes bit for bit.
@@ -85,14 +86,16 @@ def test_tau_law_matches_oracle(gpu, monkeypatch, dim, ry, rz, ndg, scheme):
     assert rel(ref.temperature(), const.temperature()) > 1e-7  # the law matters here
 
 
-@pytest.mark.parametrize("dim", ["2d", "3d"])
-def test_tau_law_fp32_matches_oracle(gpu, dim):
+@pytest.mark.parametrize("dim", ["2d", "3d", "3dn"])
+@pytest.mark.parametrize("scheme", [I.SCHEME_IMPLICIT_JACOBI, I.SCHEME_EXPLICIT_EULER])
+def test_tau_law_fp32_matches_oracle(gpu, dim, scheme):
     from oracle import Oracle
     inst = with_law(CASES[dim]())
-    ref = Oracle(inst)
+    dt = 2e-13 if scheme == I.SCHEME_EXPLICIT_EULER else inst.dt
+    ref = Oracle(inst, scheme=scheme, dt=dt)
     ref.run(3)
-    announce(f"tau(T) fp32 {inst.name}")
-    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED) as sol:
+    announce(f"tau(T) fp32 {inst.name} scheme {scheme}")
+    with gpu.Solver(inst, precision=gpu.BTE_FP32_MIXED, scheme=scheme, dt=dt) as sol:
         st = sol.step(3)
         T = sol.temperature()
     err = rel(T, ref.temperature())
