@@ -23,6 +23,76 @@
 
 using namespace bte;
 
+namespace bte {
+
+// Launch layout of a sweep: kernel family, tile shape, tile counts and
+// direction groups for a mesh (host logic; the kernels take the plan as is).
+SweepPlan make_sweep_plan(int dim, int nx, int ny, int nz, int nd, int nb, int ry, int rz,
+                          int ndg, int kind) {
+  SweepPlan pl{};
+  pl.rz = 1;
+  pl.ntz = 1;
+  if (dim == 2 && kind != kSweepCellPerThread) {
+    pl.kind = kSweepColumnWalk2D;
+    if (ry != 4 && ry != 8 && ry != 16) ry = 4;
+    pl.ry = ry;
+    pl.ntx = (nx + 63) / 64;
+    pl.nty = (ny + 4 * ry - 1) / (4 * ry);
+    pl.ntiles = pl.ntx * pl.nty;
+  } else if (dim == 3 && kind == kSweepFlat3D) {
+    pl.kind = kSweepFlat3D;
+    // 256 plane cells (4 waves x 64 lanes) x rz planes per workgroup
+    if (rz != 2 && rz != 4) rz = 4;
+    pl.ry = 0;
+    pl.rz = rz;
+    pl.ntx = (nx * ny + 255) / 256;
+    pl.nty = 1;
+    pl.ntz = (nz + rz - 1) / rz;
+    pl.ntiles = pl.ntx * pl.ntz;
+  } else if (dim == 3 && kind != kSweepCellPerThread) {
+    pl.kind = kSweepColumnWalk3D;
+    // (rows, planes) per wave: 2 x 2 (default), 1 x 4 or 2 x 4
+    if (!((ry == 2 && rz == 2) || (ry == 1 && rz == 4) || (ry == 2 && rz == 4))) {
+      ry = 2;
+      rz = 2;
+    }
+    pl.ry = ry;
+    pl.rz = rz;
+    pl.ntx = (nx + 63) / 64;
+    pl.nty = (ny + 4 * ry - 1) / (4 * ry);
+    pl.ntz = (nz + rz - 1) / rz;
+    pl.ntiles = pl.ntx * pl.nty * pl.ntz;
+  } else {
+    pl.kind = kSweepCellPerThread;
+    pl.ry = 1;
+    pl.ntx = (nx * ny * nz + kSweepBlock - 1) / kSweepBlock;
+    pl.nty = 1;
+    pl.ntiles = pl.ntx;
+    ndg = 1;
+  }
+  if (ndg <= 0) {
+    // aim for about 32 workgroups per compute unit of a 256-CU device, so the
+    // last partial round of workgroups is a small fraction of the sweep ...
+    const long long wg = (long long)pl.ntiles * nb;
+    const long long fill = std::max<long long>(1, (kSweepFillWorkgroups + wg - 1) / wg);
+    // ... but each direction group writes an 8-byte energy partial per (band,
+    // cell), which the temperature kernel reads back: keep that within 1/25 of
+    // the sweep's intensity bytes (3 x 4 bytes per direction in FP32 storage,
+    // twice that in FP64), unless the launch would drop below 4 workgroups
+    // per compute unit (a small sweep is bound by latency, not bytes)
+    const long long by_bytes = std::max<long long>(1, (3LL * nd * 4) / (8 * 25));
+    const long long quarter = std::max<long long>(1, (1024 + wg - 1) / wg);
+    ndg = (int)std::min<long long>(nd, std::min(fill, std::max(by_bytes, quarter)));
+  }
+  ndg = std::max(1, std::min(ndg, nd));
+  pl.dgs = (nd + ndg - 1) / ndg;
+  pl.ndg = (nd + pl.dgs - 1) / pl.dgs;
+  pl.nparts = pl.ntiles * nb * pl.ndg;
+  return pl;
+}
+
+}  // namespace bte
+
 namespace {
 
 thread_local std::string g_last_error;
