@@ -132,6 +132,27 @@ def copy_probe():
     log(f"copy probe: {4 * n} bytes read, {4 * n} bytes written")
 
 
+def copy_rate_gbps(reps=5):
+    """Bandwidth of a plain 1 GiB device copy (torch's copy kernel on torch's
+    current stream, timed with that stream's events; best of ``reps``): a
+    measured practical ceiling to set beside the published 8 TB/s."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (best * 1e-3) / 1e9
+
+
 def run_solo(bte, inst, prec, steps, label, timing=False, **opts):
     """Steps one fresh context ``steps`` times; returns wall time, per-step stats,
     final temperature and (with timing) the sweep-kernel time.  Logs the
@@ -390,6 +411,8 @@ def main():
         f"N_dof={inst.n_dof:.3e}, precision={args.precision}, "
         f"{'explicit' if explicit else 'implicit'}")
 
+    copy_gbps = copy_rate_gbps()
+    log(f"plain device copy: {copy_gbps:.0f} GB/s (reads + writes)")
     if args.warmup > 0:
         log(f"warmup: {args.warmup} steps on a separate context")
         with bte.Solver(inst, device="cuda:0", precision=prec) as sol:
@@ -447,6 +470,7 @@ def main():
                      "kernel": SWEEP_KERNELS[main_run["layout"]["kind"]],
                      "layout": main_run["layout"],
                      "avg_ms": avg_sweep_s * 1e3,
+                     "copy_GBps": copy_gbps,
                      "bytes_per_launch": sweep_bytes(inst, real_bytes)},
         "paper_context": dict(PAPER_CONTEXT),
     }
