@@ -179,6 +179,10 @@ __device__ __forceinline__ float read_lane(float v, int lane) {
 // row offset are wave-uniform (scalar registers), the lane offset is one vector
 // register shared by every row; reads past the slab's valid cells return 0.
 constexpr int kBufferWord3 = 0x00020000;  // gfx9-family buffer resource flags
+// A byte offset past the end of every slab (create limits a slab to
+// 2^31 - 256 bytes): a raw buffer access there reads 0 or is dropped, without
+// a memory access.
+constexpr int kPastEnd = 0x7ffffff0;
 
 // Cache-policy bits of the slab loads and stores (0: default, 2: non-temporal).
 // The new iterate is not read again within the sweep, so it is streamed out
@@ -1005,8 +1009,9 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
                                             const int bz, const int gx, const int gy) {
 #pragma clang fp contract(on)  // fuse a*b+c only within one expression
   using A = Arith<Real>;
-  // staged values carry the cell's shift when there is one
-  using L = std::conditional_t<SHIFT, A, Real>;
+  // staged in the arithmetic type (with the cell's shift, if any), so that a
+  // neighbour needs no conversion
+  using L = A;
   constexpr int sz = (int)sizeof(Real);
   constexpr int kTile = kSweepBlock;
   __shared__ L stage[2][RZ][kTile];
@@ -1186,8 +1191,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
         ik[k] = rk_v[k];
         in[k] = rn_v[k];
         if constexpr (SHIFT) ik[k] += sh[k];
-        if constexpr (SHIFT) st[k][li] = ik[k];
-        else st[k][li] = rk_v[k];
+        st[k][li] = ik[k];
       }
     }
     // the buffer written here was last read two directions ago, before every
@@ -1206,9 +1210,12 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
     const int lx = xpos ? li - 1 : li + 1;
     const int ly = fy - t0;
     const auto ro = slab_rsrc(Iob + (size_t)d * ncp, slab_bytes);
+    // lanes past the plane run the update on a valid cell's values too; their
+    // store goes past the end of the slab (dropped) and their weight is 0
+    const double wf = fok ? wd : 0.0;
 #pragma unroll
     for (int k = 0; k < RZ; ++k) {
-      if (fok && k < nplanes) {
+      if (k < nplanes) {
         const A v = ik[k];
         const A rt = TAUT ? rate[k] : a_inv_tau;
         const A q = TAUT ? static_cast<A>(cf.q) + a_expl * (a_inv_tau - rt) : static_cast<A>(cf.q);
@@ -1218,7 +1225,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
           if (xw) {
             up = xg[k];
           } else if (xin) {
-            up = static_cast<A>(st[k][lx]);
+            up = st[k][lx];
           } else {
             up = ex_r[k];
             if constexpr (SHIFT) up += shx[k];
@@ -1230,7 +1237,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
           if (yw) {
             up = yg[k];
           } else if (yin) {
-            up = static_cast<A>(st[k][ly]);
+            up = st[k][ly];
           } else {
             up = ey_r[k];
             if constexpr (SHIFT) up += ypos ? shy_p[k] : shy_n[k];
@@ -1248,13 +1255,13 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
         // iterate stops changing in storage precision its increment is zero
         const A sc = TAUT ? cell_scale(cf, p.inv_dt, rate[k], p.t.explicit_scheme) : scale;
         const Real inew_r = update_finish<Real>(acc, v, sc);
-        buf_store<Real>(inew_r, ro, vc[k], 0);
+        buf_store<Real>(inew_r, ro, fok ? vc[k] : kPastEnd, 0);
         const A inew = inew_r;
         const double da = static_cast<double>(inew - v);
         const double dn = static_cast<double>(inew - in[k]);
-        accumulate_energy<Real>(S[k], Sc[k], wd, static_cast<double>(inew));
-        num += wd * da * da;
-        den += wd * dn * dn;
+        accumulate_energy<Real>(S[k], Sc[k], wf, static_cast<double>(inew));
+        num += wf * da * da;
+        den += wf * dn * dn;
       }
     }
   }
