@@ -1,6 +1,6 @@
-"""Full-size checks at the 3D workloads' real shapes and launch layouts, where
-the oracle cannot hold the state (64^3 x 400 x 55 in FP64 is 138 GB per
-field): properties that hold at any size.
+"""Full-size checks at the 3D and batched workloads' real shapes and launch
+layouts, where the oracle cannot hold the state (64^3 x 400 x 55 in FP64 is
+138 GB per field): properties that hold at any size.
 
 * Symmetry.  A Gaussian hot spot centred in a cube with six isothermal 300 K
   walls, on a product quadrature that maps onto itself under reflection of
@@ -10,6 +10,8 @@ field): properties that hold at any size.
   it by many orders more.
 * Uniform state.  A body at 300 K with 300 K walls is the equilibrium: every
   step leaves the temperature bitwise unchanged.
+* The batch (the 64-geometry draw at full size): each geometry equals its solo
+  run bit for bit.
 """
 import sys
 
@@ -88,3 +90,48 @@ def test_fullsize_uniform_state_bitwise(gpu):
         T = sol.temperature()
     print(f"sweeps {[s['inner'] for s in st]}", flush=True)
     assert np.array_equal(T, np.full(inst.n_cells, 300.0))
+
+
+def test_c5_fullsize_batch_equals_solo(gpu, monkeypatch, tmp_path):
+    """The c5 draw at full size (64 geometries, 2.19e10 DOF, 277 GB of
+    workspace), FP32 storage, the layouts the autotuner picks for a batch, one
+    persistent launch per inner iteration replayed from a HIP graph: after 2
+    batched steps the largest 2D and 3D geometries and the smallest one equal
+    solo runs in the same layouts bit for bit (solo runs are checked against
+    the oracle on smaller meshes)."""
+    import torch
+    insts = I.config_c5(nsteps=2)
+    assert sum(i.n_dof for i in insts) > 2.1e10
+    stream = torch.cuda.Stream()
+    cache = str(tmp_path / "layouts.txt")
+    announce("c5 full draw: creating and tuning 64 contexts")
+    sols = []
+    for inst in insts:
+        s = gpu.Solver(inst, stream=stream, precision=gpu.BTE_FP32_MIXED)
+        s.autotune(cache, batch=True)
+        sols.append(s)
+    layouts = [s.sweep_layout() for s in sols]
+    announce("c5 full draw: 2 batched steps")
+    with gpu.Batch(sols, use_graph=True) as batch:
+        st = batch.step(2)
+    dofs = [i.n_dof for i in insts]
+    pick = [max((k for k in range(64) if insts[k].dim == 2), key=dofs.__getitem__),
+            max((k for k in range(64) if insts[k].dim == 3), key=dofs.__getitem__),
+            min(range(64), key=dofs.__getitem__)]
+    T_batch = {k: sols[k].temperature() for k in pick}
+    for s in sols:
+        s.close()
+    del sols
+    torch.cuda.empty_cache()
+    for k in pick:
+        lay = layouts[k]
+        for name, v in (("BTE_SWEEP_KIND", lay["kind"]), ("BTE_SWEEP_RY", lay["ry"]),
+                        ("BTE_SWEEP_RZ", lay["rz"]), ("BTE_SWEEP_NDG", lay["ndg"])):
+            monkeypatch.setenv(name, str(v))
+        announce(f"c5 geometry {k} ({insts[k].name}, {dofs[k]:.3e} DOF, layout {lay}) solo")
+        with gpu.Solver(insts[k], stream=stream, precision=gpu.BTE_FP32_MIXED) as s:
+            assert s.sweep_layout() == lay
+            solo = s.step(2)
+            T = s.temperature()
+        assert [x["inner"] for x in solo] == [st[j][k]["inner"] for j in range(2)]
+        assert np.array_equal(T, T_batch[k]), float(np.max(np.abs(T - T_batch[k])))
