@@ -59,18 +59,28 @@ def sweep_bytes(inst, real_bytes):
     return inst.n_dof * per_update + inst.n_bands * inst.n_cells * per_band_cell
 
 
+def kernel_code_hash(path):
+    """sha256 of a HIP source without its comments and blank lines: an edit
+    of the comments leaves the compiled kernels, and so the counters taken on
+    them, as they were."""
+    import hashlib
+    import re
+    with open(path) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+    return hashlib.sha256("\n".join(l for l in lines if l.strip()).encode()).hexdigest()
+
+
 def measured_traffic(kernel_file, counters_file):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was measured on the kernel source as it is now; else None."""
-    import hashlib
+    if it was measured on the kernel code as it is now; else None."""
     try:
         with open(counters_file) as f:
             c = json.load(f)
-        with open(kernel_file, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        code = kernel_code_hash(kernel_file)
     except (OSError, ValueError):
         return None
-    if c.get("kernel_source_sha256") != sha:
+    if c.get("kernel_code_sha256") != code:
         return None
     return c.get("traffic_bytes_per_launch")
 

@@ -998,11 +998,11 @@ __global__ __launch_bounds__(kSweepBlock) void sweep3d_walk_kernel(const SweepPa
 // direction): a neighbour inside the tile is read from there, and only the
 // tile's halo (the row before its first or after its last cell, and the cell
 // beyond either end) is loaded from memory.  Without the staging every wave
-// loaded the rows and edge cells that its neighbour waves load at the same
-// time, and those duplicate requests went out to memory as well.  Lanes on an
-// x or y wall take the ghost (isothermal equilibrium in storage format, or
-// the cell's own intensity in the mirrored direction) from a load masked to
-// them.
+// loaded rows and edge cells that its neighbour waves load too; with no
+// barrier between them the waves drift apart by several directions, and the
+// second reads missed L2.  Lanes on an x or y wall take the ghost (isothermal
+// equilibrium in storage format, or the cell's own intensity in the mirrored
+// direction) from a load masked to them.
 template <typename Real, int RZ, bool SHIFT, bool TAUT>
 __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const int nft,
                                             const int dgs, const int bx, const int by,

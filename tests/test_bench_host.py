@@ -1,7 +1,6 @@
 """Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
 bytes per sweep launch, and the rule that measured traffic is reported only
 for the kernel source it was measured on."""
-import hashlib
 import json
 import os
 import subprocess
@@ -38,13 +37,16 @@ def test_sweep_bytes_of_the_2d_workload():
 
 def test_traffic_only_for_the_measured_source(tmp_path):
     src = tmp_path / "kernels.hip"
-    src.write_bytes(b"__global__ void k() {}\n")
-    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    src.write_text("// a kernel\n__global__ void k() {}  // empty\n")
     counters = tmp_path / "counters.json"
-    counters.write_text(json.dumps({"kernel_source_sha256": sha,
+    counters.write_text(json.dumps({"kernel_code_sha256": bench.kernel_code_hash(str(src)),
                                     "traffic_bytes_per_launch": 1.25e9}))
     assert bench.measured_traffic(str(src), str(counters)) == 1.25e9
-    src.write_bytes(b"__global__ void k() { }\n")  # source changed since the counters
+    # comments and blank lines do not count ...
+    src.write_text("/* a kernel,\n   empty */\n\n__global__ void k() {}\n")
+    assert bench.measured_traffic(str(src), str(counters)) == 1.25e9
+    # ... code does
+    src.write_text("__global__ void k() { }\n")
     assert bench.measured_traffic(str(src), str(counters)) is None
     assert bench.measured_traffic(str(src), str(tmp_path / "missing.json")) is None
     counters.write_text("not json")
