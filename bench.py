@@ -47,6 +47,9 @@ PAPER_CONTEXT = {
     "workload": "2D 120 x 120 cells, 20 directions x 55 band entries (~1.6e7 DOF), "
                 "forward Euler, 100 steps",
     "source": "paper Abstract and Sec. 3.4 (GPU results)",
+    # the paper's profile of its one-GPU run, beside this sweep's roofline
+    "paper_gpu_profile": {"sm_utilization": 0.86, "memory_throughput_of_peak": 0.11,
+                          "flop_of_peak": 0.49, "source": "paper Sec. 3.4"},
 }
 
 
