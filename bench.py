@@ -310,6 +310,7 @@ def run_c5(args):
     del sols
     inner_b = [sum(st[g]["inner"] for st in per_step) for g in range(len(insts))]
     updates_b = sum(k * i.n_dof for k, i in zip(inner_b, insts))
+    sweep_bytes_b = sum(k * sweep_bytes(i, 4) for k, i in zip(inner_b, insts))
 
     wall_s, inner_s, after_s, err = 0.0, [], 0, 0.0
     for g, inst in enumerate(insts):
@@ -342,13 +343,15 @@ def run_c5(args):
                    "launch": "persistent sweep + HIP graph per inner iteration"},
         "time_to_solution_s": wall_b,
         "inner_sweeps": sum(inner_b),
+        "batch_sweep_bytes": sweep_bytes_b,
         "sequential_fp64": {"value": updates_s / wall_s, "unit": "updates/s",
                             "time_to_solution_s": wall_s, "inner_sweeps": sum(inner_s),
                             "speedup_time_to_solution": wall_s / wall_b,
                             "T_max_rel_err_batch_vs_fp64": err},
         "roofline": None,
-        "note": "per-launch timing is off inside batches; the sweep roofline is reported "
-                "by the single-geometry workloads",
+        "note": "per-launch timing is off inside batches; batch_sweep_bytes (algorithmic "
+                "bytes of every batched sweep) over the batched sweep kernels' time in a "
+                "rocprofv3 kernel trace gives their bandwidth",
     }
     if steps > train:
         out["inner_sweeps_after_training"] = {"batch_fp32_warm": warm, "sequential_fp64": after_s}
