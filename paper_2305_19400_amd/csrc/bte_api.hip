@@ -127,7 +127,7 @@ struct Layout {
 };
 
 struct Shape {
-  int dim, nx, ny, nz, nc, ncp, nd, nb;
+  int dim, nx, ny, nz, nc, ncp, px, nd, nb;  // as in Geometry
   int nf[6];
   bool iso[6];   // isothermal: face temperatures given
   bool diff[6];  // diffuse: ghost table recomputed every iteration
@@ -266,7 +266,18 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   s.ny = m->n[1];
   s.nz = m->n[2];
   s.nc = (int)nc;
-  s.ncp = (int)((nc + kSlabAlign - 1) / kSlabAlign * kSlabAlign);
+  {
+    // 2D: intensity rows padded to a 128-byte line of stored values
+    const long long line = o->precision == BTE_FP64 ? 16 : 32;
+    const long long px = s.dim == 2 ? (s.nx + line - 1) / line * line : s.nx;
+    const long long ncp =
+        s.dim == 2 ? px * s.ny : (nc + kSlabAlign - 1) / kSlabAlign * kSlabAlign;
+    if (ncp > kMaxCells)
+      return fail(BTE_E_INVAL, "too many cells with padding (%lld; at most %lld)", ncp,
+                  (long long)kMaxCells);
+    s.px = (int)px;
+    s.ncp = (int)ncp;
+  }
   s.nd = d->n;
   s.nb = b->n;
   // Launch layout of the sweep; BTE_SWEEP_RY / BTE_SWEEP_RZ / BTE_SWEEP_NDG /
@@ -1013,6 +1024,7 @@ int bte_create(const bte_mesh* mesh, const bte_dirs* dirs, const bte_bands* band
   g.nz = s.nz;
   g.nc = s.nc;
   g.ncp = s.ncp;
+  g.px = s.px;
   g.nd = nd;
   g.nb = nb;
   g.ndg = s.plan.ndg;
@@ -1168,6 +1180,21 @@ int bte_step(bte_ctx* ctx, int nsteps, const int* fixed_inner, bte_step_stats* s
   return BTE_OK;
 }
 
+// Copies the intensity field between a dense [b][d][P] array of stored
+// values and the device slabs (ncp cells apart; on 2D meshes with padded rows,
+// rows of nx cells px apart, and ncp = px ny).
+static hipError_t copy_intensity(void* dst, const void* src, const Shape& s, hipMemcpyKind kind,
+                                 hipStream_t stream) {
+  const size_t sz = s.real_size, slabs = (size_t)s.nb * s.nd;
+  const bool rows = s.px != s.nx;
+  const size_t width = rows ? (size_t)s.nx : (size_t)s.nc;
+  const size_t pitch = rows ? (size_t)s.px : (size_t)s.ncp;
+  const size_t height = rows ? slabs * s.ny : slabs;
+  const bool to_device = kind == hipMemcpyHostToDevice;
+  return hipMemcpy2DAsync(dst, sz * (to_device ? pitch : width), src,
+                          sz * (to_device ? width : pitch), sz * width, height, kind, stream);
+}
+
 static int copy_cells(bte_ctx* ctx, const double* src, double* dst, size_t n) {
   if (!ctx) return fail(BTE_E_INVAL, "null context");
   if (ctx->poisoned) return fail(BTE_E_DEVICE, "context is poisoned");
@@ -1200,9 +1227,7 @@ int bte_intensity(bte_ctx* ctx, double* I_out, size_t n) {
   if (n != rows * ctx->s.nc)
     return fail(BTE_E_INVAL, "expected %zu intensities, got %zu", rows * ctx->s.nc, n);
   if (ctx->opt.precision == BTE_FP64) {
-    HIP_TRY(hipMemcpy2DAsync(I_out, sizeof(double) * ctx->s.nc, ctx->In,
-                             sizeof(double) * ctx->s.ncp, sizeof(double) * ctx->s.nc, rows,
-                             hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(copy_intensity(I_out, ctx->In, ctx->s, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
   } else {
     std::vector<float> tmp;
@@ -1211,9 +1236,7 @@ int bte_intensity(bte_ctx* ctx, double* I_out, size_t n) {
     } catch (...) {
       return fail(BTE_E_NOMEM, "out of host memory");
     }
-    HIP_TRY(hipMemcpy2DAsync(tmp.data(), sizeof(float) * ctx->s.nc, ctx->In,
-                             sizeof(float) * ctx->s.ncp, sizeof(float) * ctx->s.nc, rows,
-                             hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(copy_intensity(tmp.data(), ctx->In, ctx->s, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     const size_t nc = ctx->s.nc;
     for (size_t i = 0; i < n; ++i) I_out[i] = ctx->Iref[i / (nc * ctx->s.nd)] + (double)tmp[i];
@@ -1232,8 +1255,7 @@ int bte_set_fields(bte_ctx* ctx, const double* I, size_t n, const double* T, siz
     if (!(T[P] > 0.0) || !std::isfinite(T[P]))
       return fail(BTE_E_INVAL, "T[%zu] must be positive", P);
   if (ctx->opt.precision == BTE_FP64) {
-    HIP_TRY(hipMemcpy2DAsync(ctx->In, sizeof(double) * ctx->s.ncp, I, sizeof(double) * ctx->s.nc,
-                             sizeof(double) * ctx->s.nc, rows, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(copy_intensity(ctx->In, I, ctx->s, hipMemcpyHostToDevice, ctx->stream));
   } else {
     std::vector<float> tmp;
     try {
@@ -1244,9 +1266,7 @@ int bte_set_fields(bte_ctx* ctx, const double* I, size_t n, const double* T, siz
     const size_t nc = ctx->s.nc;
     for (size_t i = 0; i < n; ++i)
       tmp[i] = static_cast<float>(I[i] - ctx->Iref[i / (nc * ctx->s.nd)]);
-    HIP_TRY(hipMemcpy2DAsync(ctx->In, sizeof(float) * ctx->s.ncp, tmp.data(),
-                             sizeof(float) * ctx->s.nc, sizeof(float) * ctx->s.nc, rows,
-                             hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(copy_intensity(ctx->In, tmp.data(), ctx->s, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
   }
   HIP_TRY(hipMemcpyAsync(ctx->T, T, sizeof(double) * n_cells, hipMemcpyHostToDevice, ctx->stream));
@@ -1348,12 +1368,11 @@ int bte_get_state(bte_ctx* ctx, void* buf, size_t bytes) {
   char* out = static_cast<char*>(buf);
   memcpy(out, &h, sizeof h);
   const Shape& s = ctx->s;
-  const size_t nc = s.nc, rows = (size_t)s.nb * s.nd;
+  const size_t nc = s.nc;
   auto d2h = [&](int sec, const void* src, size_t n) {
     return hipMemcpyAsync(out + h.off[sec], src, n, hipMemcpyDeviceToHost, ctx->stream);
   };
-  HIP_TRY(hipMemcpy2DAsync(out + h.off[kSecI], s.real_size * nc, ctx->In, s.real_size * s.ncp,
-                           s.real_size * nc, rows, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(copy_intensity(out + h.off[kSecI], ctx->In, s, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(d2h(kSecT, ctx->T, sizeof(double) * nc));
   HIP_TRY(d2h(kSecTprev, ctx->Tprev, sizeof(double) * nc));
   HIP_TRY(d2h(kSecE, ctx->E, sizeof(double) * nc));
@@ -1407,12 +1426,11 @@ int bte_set_state(bte_ctx* ctx, const void* buf, size_t bytes) {
                 "(another coldest input temperature)");
   if (h.nn_recorded < 0 || h.nn_recorded > h.nn_rec || h.nn_adam_t < 0 || h.steps < 0)
     return fail(BTE_E_STATE, "state counters out of range");
-  const size_t nc = s.nc, rows = (size_t)s.nb * s.nd;
+  const size_t nc = s.nc;
   auto h2d = [&](void* dst, int sec, size_t n) {
     return hipMemcpyAsync(dst, in + h.off[sec], n, hipMemcpyHostToDevice, ctx->stream);
   };
-  HIP_TRY(hipMemcpy2DAsync(ctx->In, s.real_size * s.ncp, in + h.off[kSecI], s.real_size * nc,
-                           s.real_size * nc, rows, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(copy_intensity(ctx->In, in + h.off[kSecI], s, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(h2d(ctx->T, kSecT, sizeof(double) * nc));
   HIP_TRY(h2d(ctx->Tprev, kSecTprev, sizeof(double) * nc));
   HIP_TRY(h2d(ctx->E, kSecE, sizeof(double) * nc));

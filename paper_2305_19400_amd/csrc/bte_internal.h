@@ -42,8 +42,6 @@ struct Control {
   double den;      // last ||I^{k+1} - I^n||^2
 };
 
-// Per (band, direction) sweep coefficients: c[a] = v_b |s_{d,a}| / h_a and the
-// update scale (1 / diagonal for Jacobi, dt for forward Euler).
 // Per (band, direction): c_a = v_b |s_{d,a}| / h_a; scale = 1 / (1/dt + 1/tau_b +
 // sum_a c_a) (backward Euler) or dt (forward Euler); q = the coefficient of
 // I^n in the direct form of the FP32-storage update: 1/dt, or
@@ -59,15 +57,27 @@ static_assert(sizeof(Coef) == 5 * sizeof(double), "Coef is read as five contiguo
 __host__ __device__ inline bool dir_pos(int flags, int a) { return (flags >> a) & 1; }
 __host__ __device__ inline bool dir_neg(int flags, int a) { return (flags >> (4 + a)) & 1; }
 
+// Cell P = x + nx (y + ny z).  Per-cell arrays ([b][P]) hold nc values in
+// rows of ncp; an intensity slab ([b][d][.]) holds cell P at x + px (y + ny z):
+// on 2D meshes px is nx rounded up to a 128-byte line of stored values, so
+// every row of a slab starts on a line (rows that straddle lines cost the
+// column walk 20-40 %), and ncp = px ny; on 3D meshes px = nx and ncp is nc
+// rounded up to kSlabAlign.
 struct Geometry {
   int dim;
   int nx, ny, nz;
   int nc;    // cells
-  int ncp;   // padded cells per slab
+  int ncp;   // cells per slab, padding included
+  int px;    // intensity row pitch in cells
   int nd, nb;
   int ndg;   // direction groups of the energy partials S[ndg][nb][ncp]
   double vol;
 };
+
+// Position of cell P in an intensity slab.
+__host__ __device__ inline size_t ipos(const Geometry& g, size_t P) {
+  return g.px == g.nx ? P : (P / g.nx) * g.px + P % g.nx;
+}
 
 // How a sweep is laid out on the device.
 enum SweepKind {

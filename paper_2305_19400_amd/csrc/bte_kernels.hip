@@ -289,12 +289,15 @@ __device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int
   const double I0P = p.I0[(size_t)b * ncp + Pc];
   const double inv_tau = TAUT ? p.t.relax[(size_t)b * ncp + Pc] : cld(p.t.inv_tau, (size_t)b);
   const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
-  const int slab_bytes = g.nc * (int)sizeof(Real);
-  const int voff = Pc * (int)sizeof(Real);
-  // Per axis: coordinate, extent, cell stride and wall-face index of this cell.
+  const int slab_bytes = g.px * g.ny * g.nz * (int)sizeof(Real);
+  const int Qc = (int)ipos(g, Pc);  // this cell's position in a slab
+  const int voff = Qc * (int)sizeof(Real);
+  // Per axis: coordinate, extent, cell stride (per-cell arrays, slabs) and
+  // wall-face index of this cell.
   const int co[3] = {cx, cy, cz};
   const int ext[3] = {g.nx, g.ny, g.nz};
   const int str[3] = {1, g.nx, g.nx * g.ny};
+  const int istr[3] = {1, g.px, g.px * g.ny};
   const int face[3] = {cy + g.ny * cz, cx + g.nx * cz, cx + g.nx * cy};
   double sh0 = 0.0, shn[DIM][2];  // warm-start shift of this cell and its neighbours
   if constexpr (SHIFT) {
@@ -331,8 +334,8 @@ __device__ __forceinline__ void sweep_body(const SweepParams<Real>& p, const int
       const int side = 2 * a + (minus[a] ? 0 : 1);
       iso[a] = p.t.wall[side] == 0;
       const int r = iso[a] ? d : cld(p.t.mirror, (size_t)a * g.nd + d);
-      const Real* src = inside[a] ? slab + (minus[a] ? Pc - str[a] : Pc + str[a])
-                                  : Ikb + (size_t)r * ncp + Pc;
+      const Real* src = inside[a] ? slab + (minus[a] ? Qc - istr[a] : Qc + istr[a])
+                                  : Ikb + (size_t)r * ncp + Qc;
       nb_r[a] = *src;
       const double* __restrict__ wtab = iso[a] ? p.t.wall_I0[side] : p.t.w;
       wt[a] = wtab[iso[a] ? (size_t)b * p.t.wall_nf[side] + face[a] : 0];
@@ -432,21 +435,24 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   Real* __restrict__ Iob = p.Iout + band_off;
   const double inv_tau = p.t.inv_tau[b];
   const double iref = Storage<Real>::kDeviation ? p.t.Iref[b] : 0.0;
-  const int slab_bytes = g.nc * (int)sizeof(Real);
+  const int px = g.px;  // slab row pitch (rows start on a 128-byte line)
+  const int slab_bytes = px * ny * (int)sizeof(Real);
   // Every lane and row addresses a valid cell: lanes past the mesh edge reuse
   // column x0 and rows past the mesh reuse this wave's first row (their values
   // are never used), so no access leaves the slab's valid cells.
   const int voff = (colok ? lane : 0) * (int)sizeof(Real);
   const int y0c = min(y0, ny - 1);
-  const int row0 = (y0c * nx + x0) * (int)sizeof(Real);  // byte offset of (x0, y0)
-  const int rowb = nx * (int)sizeof(Real);
+  const int row0 = (y0c * px + x0) * (int)sizeof(Real);  // byte offset of (x0, y0)
+  const int rowb = px * (int)sizeof(Real);
   int rowoff[RY];  // byte offset of (x0, row j) in a slab
   int vrow[RY];    // this lane's byte offset in row j (offsets live in VGPRs, so the
                    // slab loads never need a uniform register for them)
+  int celloff[RY];  // byte offset of (x0, row j) in a per-cell FP64 array
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
     rowoff[j] = row0 + (j < nrows ? j : 0) * rowb;
     vrow[j] = voff + rowoff[j];
+    celloff[j] = ((y0c + (j < nrows ? j : 0)) * nx + x0) * 8;
   }
 
   using A = Arith<Real>;
@@ -457,14 +463,14 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       const auto v = __builtin_amdgcn_raw_buffer_load_b64(r0, (colok ? lane : 0) * 8,
-                                                          rowoff[j] / (int)sizeof(Real) * 8, 0);
+                                                          celloff[j], 0);
       I0r[j] = to_arith<Real>(iref,
                               __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]));
       rate[j] = inv_tau;
       if constexpr (TAUT) {
         const auto r2 = slab_rsrc(p.t.relax + (size_t)b * ncp, g.nc * 8);
         const auto u = __builtin_amdgcn_raw_buffer_load_b64(r2, (colok ? lane : 0) * 8,
-                                                            rowoff[j] / (int)sizeof(Real) * 8, 0);
+                                                            celloff[j], 0);
         rate[j] = __longlong_as_double(((long long)u[1] << 32) | (unsigned int)u[0]);
       }
       S[j] = 0.0;
@@ -473,7 +479,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
       if constexpr (SHIFT) {
         const auto r1 = slab_rsrc(p.shift + (size_t)b * ncp, g.nc * 8);
         const auto u = __builtin_amdgcn_raw_buffer_load_b64(r1, (colok ? lane : 0) * 8,
-                                                            rowoff[j] / (int)sizeof(Real) * 8, 0);
+                                                            celloff[j], 0);
         sh[j] = static_cast<A>(__longlong_as_double(((long long)u[1] << 32) | (unsigned int)u[0]));
       }
     }
@@ -553,7 +559,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     const bool iso_x = wx && p.t.wall[sx] == 0;
     const int dx_src = (wx && !iso_x) ? cld(p.t.mirror, (size_t)d) : d;
     const Real ex_r = buf_load_raw<Real>(slab_rsrc(Ikb + (size_t)dx_src * ncp, slab_bytes),
-                                         (ye * nx + (xpos ? col_l : col_r)) * (int)sizeof(Real));
+                                         (ye * px + (xpos ? col_l : col_r)) * (int)sizeof(Real));
     const Real* __restrict__ wbx =  // valid either way
         iso_x ? static_cast<const Real*>(p.t.wall_S[sx]) : reinterpret_cast<const Real*>(p.t.w);
     const Real ex_w = wbx[iso_x ? (size_t)b * p.t.wall_nf[sx] + ye : 0];
@@ -562,7 +568,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
     const bool iso_y = wy && p.t.wall[sy] == 0;
     const int dy_src = (wy && !iso_y) ? cld(p.t.mirror, (size_t)g.nd + d) : d;
     const Real ey_r = buf_load_raw<Real>(slab_rsrc(Ikb + (size_t)dy_src * ncp, slab_bytes),
-                                         ((ypos ? row_p : row_n) * nx + xcol) * (int)sizeof(Real));
+                                         ((ypos ? row_p : row_n) * px + xcol) * (int)sizeof(Real));
     const Real* __restrict__ wby =
         iso_y ? static_cast<const Real*>(p.t.wall_S[sy]) : reinterpret_cast<const Real*>(p.t.w);
     const Real ey_w = wby[iso_y ? (size_t)b * p.t.wall_nf[sy] + xcol : 0];
@@ -712,7 +718,7 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
   Real* __restrict__ Iob = p.Iout + band_off;
   const double inv_tau = cld(p.t.inv_tau, (size_t)b);
   const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
-  const int slab_bytes = g.nc * sz;
+  const int slab_bytes = g.nc * sz;  // 3D slabs have no row padding (px = nx)
   // Register cell (j, k) is row y0 + j of plane z0 + k; rows and planes past
   // the mesh reuse the last valid one (their values are never used), so every
   // access stays on valid cells.
@@ -1045,7 +1051,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
   Real* __restrict__ Iob = p.Iout + band_off;
   const double inv_tau = cld(p.t.inv_tau, (size_t)b);
   const double iref = Storage<Real>::kDeviation ? cld(p.t.Iref, (size_t)b) : 0.0;
-  const int slab_bytes = g.nc * sz;
+  const int slab_bytes = g.nc * sz;  // 3D slabs have no row padding (px = nx)
   // planes past the mesh reuse the last valid one (their values are never used)
   int zp[RZ], vc[RZ];
 #pragma unroll
@@ -1734,7 +1740,7 @@ __global__ void diffuse_wall_kernel(Geometry g, Tables t, int side, const double
   double dev = 0.0;
   for (int d = 0; d < g.nd; ++d) {
     const double wd = wts[d];
-    if (wd > 0.0) dev += wd * static_cast<double>(I[((size_t)b * g.nd + d) * ncp + P]);
+    if (wd > 0.0) dev += wd * static_cast<double>(I[((size_t)b * g.nd + d) * ncp + ipos(g, P)]);
   }
   if (shift) dev += shift[(size_t)b * ncp + P];
   wall_I0[(size_t)b * nf + f] = ref + dev;
@@ -1800,13 +1806,16 @@ template <typename Real>
 __global__ __launch_bounds__(256) void broadcast_kernel(Geometry g, const double* __restrict__ I0,
                                                         const double* __restrict__ Iref,
                                                         Real* __restrict__ I) {
-  const int P = blockIdx.x * 256 + threadIdx.x;
+  const int Q = blockIdx.x * 256 + threadIdx.x;  // position in the slab
   const int d = blockIdx.y;
   const int b = blockIdx.z;
-  if (P >= g.ncp) return;
+  if (Q >= g.ncp) return;
+  const int x = Q % g.px, r = Q / g.px;  // column and row (y + ny z)
+  const bool cell = x < g.nx && r < g.ny * g.nz;
   const double ref = Storage<Real>::kDeviation ? Iref[b] : 0.0;
-  I[((size_t)b * g.nd + d) * g.ncp + P] =
-      (P < g.nc) ? encode<Real>(ref, I0[(size_t)b * g.ncp + P]) : static_cast<Real>(0);
+  I[((size_t)b * g.nd + d) * g.ncp + Q] =
+      cell ? encode<Real>(ref, I0[(size_t)b * g.ncp + (size_t)r * g.nx + x])
+           : static_cast<Real>(0);
 }
 
 template <typename Real>
@@ -1844,12 +1853,13 @@ __global__ __launch_bounds__(kCellBlock) void energy_kernel(Geometry g, Tables t
                                                             double* __restrict__ E) {
   const int P = blockIdx.x * kCellBlock + threadIdx.x;
   if (P >= g.nc) return;
+  const size_t Q = ipos(g, P);
   CompSum e;
   for (int b = 0; b < g.nb; ++b) {
     const double ref = Storage<Real>::kDeviation ? t.Iref[b] : 0.0;
     CompSum s;
     for (int d = 0; d < g.nd; ++d)
-      s.add(t.w[d] * decode(ref, I[((size_t)b * g.nd + d) * g.ncp + P]));
+      s.add(t.w[d] * decode(ref, I[((size_t)b * g.nd + d) * g.ncp + Q]));
     e.add(s.value());
   }
   E[P] = e.value();
