@@ -62,25 +62,37 @@ def sweep_bytes(inst, real_bytes):
     return inst.n_dof * per_update + inst.n_bands * inst.n_cells * per_band_cell
 
 
-def kernel_code_hash(path):
-    """sha256 of a HIP source without its comments and blank lines: an edit
+# The sources the sweep kernels compile from: the kernels and the header of
+# the structures, constants and helpers they use.
+KERNEL_SOURCES = tuple(os.path.join(ROOT, "paper_2305_19400_amd", "csrc", f)
+                       for f in ("bte_kernels.hip", "bte_internal.h"))
+
+
+def kernel_code_hash(*paths):
+    """sha256 of HIP sources without their comments and blank lines: an edit
     of the comments leaves the compiled kernels, and so the counters taken on
     them, as they were."""
     import hashlib
     import re
-    with open(path) as f:
-        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
-    lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
-    return hashlib.sha256("\n".join(l for l in lines if l.strip()).encode()).hexdigest()
+    parts = []
+    for path in paths:
+        with open(path) as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+        parts.append("\n".join(l for l in lines if l.strip()))
+    return hashlib.sha256("\n\f\n".join(parts).encode()).hexdigest()
 
 
-def measured_traffic(kernel_file, counters_file):
+def measured_traffic(sources, counters_file):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was measured on the kernel code as it is now; else None."""
+    if it was measured on the kernel code (``sources``: one path or several)
+    as it is now; else None."""
+    if isinstance(sources, str):
+        sources = (sources,)
     try:
         with open(counters_file) as f:
             c = json.load(f)
-        code = kernel_code_hash(kernel_file)
+        code = kernel_code_hash(*sources)
     except (OSError, ValueError):
         return None
     if c.get("kernel_code_sha256") != code:
@@ -495,8 +507,7 @@ def main():
     key = (args.workload, args.precision)
     if key in COUNTERS:
         out["roofline"]["traffic"] = measured_traffic(
-            os.path.join(ROOT, "paper_2305_19400_amd", "csrc", "bte_kernels.hip"),
-            os.path.join(ROOT, "profiles", COUNTERS[key]))
+            KERNEL_SOURCES, os.path.join(ROOT, "profiles", COUNTERS[key]))
     if prec == bte.BTE_FP32_MIXED and wl["fp64_fits"]:
         # the FP32 result's error against FP64 storage at the same tolerance
         torch.cuda.empty_cache()

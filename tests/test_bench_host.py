@@ -53,6 +53,27 @@ def test_traffic_only_for_the_measured_source(tmp_path):
     assert bench.measured_traffic(str(src), str(counters)) is None
 
 
+def test_traffic_tracks_the_kernel_header(tmp_path):
+    """The kernels compile from a header too: a change of its code voids the
+    counters, a change of its comments does not."""
+    src, hdr = tmp_path / "kernels.hip", tmp_path / "internal.h"
+    src.write_text("__global__ void k() {}\n")
+    hdr.write_text("constexpr int kBlock = 256;  // threads\n")
+    counters = tmp_path / "counters.json"
+    counters.write_text(json.dumps({"kernel_code_sha256": bench.kernel_code_hash(str(src), str(hdr)),
+                                    "traffic_bytes_per_launch": 2.5e9}))
+    files = (str(src), str(hdr))
+    assert bench.measured_traffic(files, str(counters)) == 2.5e9
+    hdr.write_text("// block size\nconstexpr int kBlock = 256;\n")
+    assert bench.measured_traffic(files, str(counters)) == 2.5e9
+    hdr.write_text("constexpr int kBlock = 128;\n")
+    assert bench.measured_traffic(files, str(counters)) is None
+    assert bench.measured_traffic(str(src), str(counters)) is None
+    # the shipped sources are the kernels and their header
+    assert [os.path.basename(f) for f in bench.KERNEL_SOURCES] == ["bte_kernels.hip",
+                                                                   "bte_internal.h"]
+
+
 def test_sweep_bytes_of_the_explicit_paper_demo():
     # forward Euler reads I^n once and writes I^{n+1}
     inst = I.config_f1()
