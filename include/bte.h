@@ -342,9 +342,13 @@ int bte_nn_gradient(bte_ctx* ctx, const double* T_n, const double* T_prev, const
  * groups; 3D layouts: 2x2, 1x4 or 2x4 (rows x planes held per wave), or 4 or
  * 2 planes of the flattened (x, y) plane (reported as 0 rows), x 1-4
  * direction groups.  *ry and *rz are in/out: a positive value on entry
- * restricts the search to that row / plane count, and *ry = -1 to the layouts
- * a batch accepts (4 rows in 2D; 2x2, 1x4 or the flattened plane in 3D).
- * The choice is returned in *ry, *rz, *ndg and its sweep time (measured now
+ * restricts the search to that row / plane count, and *ry = -1 tunes for a
+ * batch: one direction group, 4 rows in 2D, and in 3D 4 planes per wave of
+ * the family create picks by idle lanes (the flattened plane where 64-column
+ * tiles leave more than an eighth of the lanes idle, else the 1x4 walk).  In
+ * a batch the geometries fill the device together, so layouts that spread
+ * one sweep wider only add bytes; batch choices are cached apart from
+ * single-geometry ones.  The choice is returned in *ry, *rz, *ndg and its sweep time (measured now
  * or recorded in the cache) in *sweep_ms (all nullable; -1 for
  * shapes with a single layout).  BTE_E_INVAL if the restriction matches no
  * layout. */

@@ -138,6 +138,14 @@ struct Shape {
   int nn_rec;     // recorded steps before training
 };
 
+// 3D: whether 64-column tiles would leave more than an eighth of the lanes
+// idle (a narrow mesh or a ragged last tile), where the flattened (x, y)
+// plane is the default family.
+bool flat_by_lanes(int nx) {
+  const double lanes_used = (double)nx / (64.0 * ((nx + 63) / 64));
+  return lanes_used < 0.875;
+}
+
 // The layouts a batched persistent sweep compiles: 4 rows per wave in 2D;
 // in 3D 2 rows x 2 planes or 1 row x 4 planes per wave, or the flattened
 // (x, y) plane with 2 or 4 planes per wave.
@@ -294,8 +302,7 @@ int validate(const bte_mesh* m, const bte_dirs* d, const bte_bands* b, const bte
   const bool fp32 = o->precision != BTE_FP64;
   int ry_dflt = 0, rz_dflt = 0, kind_dflt = -1;
   if (s.dim == 3) {
-    const double lanes_used = (double)s.nx / (64.0 * ((s.nx + 63) / 64));
-    if (lanes_used < 0.875) {
+    if (flat_by_lanes(s.nx)) {
       kind_dflt = kSweepFlat3D;
       const long long tiles4 =
           ((long long)s.nx * s.ny + 255) / 256 * ((s.nz + 3) / 4) * (long long)s.nb;
@@ -1670,6 +1677,25 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
   };
   const int ry_only = ry_out ? *ry_out : 0;
   const int rz_only = rz_out ? *rz_out : 0;
+  // In a batch the geometries fill the device together, and a geometry timed
+  // alone is a poor guide: it favours layouts that spread a small sweep over
+  // more workgroups (more direction groups, 2 planes per wave instead of 4),
+  // which in a batch only cost bytes (energy partials for the temperature
+  // kernel to read back, tile faces).  A batch tune therefore takes one
+  // direction group, 4 rows in 2D, and in 3D the family that create picks by
+  // idle lanes (the flattened plane where 64-column tiles would leave more
+  // than an eighth of the lanes idle, else the column walk) with 4 planes
+  // per wave.  Measured on the 64-geometry draw, 4 steps: 3.49 s with the
+  // layouts that time fastest alone, 3.31 s timing the two 4-plane families
+  // at one group, 3.19-3.22 s with this choice.
+  if (ry_only == -1) {
+    groups = {1};
+    if (family3d)
+      shapes = {flat_by_lanes(ctx->s.nx) ? std::make_pair(0, 4) : std::make_pair(1, 4)};
+  }
+  auto listed_groups = [&](int ndg) {
+    return std::find(groups.begin(), groups.end(), ndg) != groups.end();
+  };
   auto allowed = [&](int ry, int rz) {
     bool listed = false;
     for (const auto& sh : shapes) listed |= (sh.first == ry && sh.second == rz);
@@ -1683,7 +1709,7 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
   auto fits = [&](const SweepPlan& pl) {
     return pl.ndg <= ctx->s.ndg_cap && pl.nparts <= ctx->s.nparts_cap;
   };
-  const std::string key = tune_key(ctx);
+  const std::string key = tune_key(ctx) + (ry_only == -1 ? " batch" : "");
   SweepPlan best = ctx->s.plan;
   double best_ms = -1.0;
   bool found = shapes.empty();  // a single-layout family needs no search
@@ -1696,7 +1722,7 @@ int bte_autotune(bte_ctx* ctx, const char* cache_path, int* ry_out, int* rz_out,
         int ry = 0, rz = 0, ndg = 0;
         double ms = 0.0;
         if (sscanf(sep + 4, "ry=%d rz=%d ndg=%d ms=%lf", &ry, &rz, &ndg, &ms) == 4 &&
-            allowed(ry, rz)) {
+            allowed(ry, rz) && listed_groups(ndg)) {
           const SweepPlan pl = plan_for(ry, rz, ndg);
           if (fits(pl)) {
             best = pl;

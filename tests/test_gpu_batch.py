@@ -261,9 +261,15 @@ def test_autotune_picks_a_layout_and_caches_it(gpu, dim):
                 s2.autotune(None, ry=3)  # no such layout
         assert open(cache).read() == text
         with gpu.Solver(inst) as s3:  # restricted to what a batch accepts
-            ry, rz, ndg, ms = s3.autotune(None, batch=True)
-            assert (ry, rz) in ({(4, 1)} if dim == 2 else {(2, 2), (1, 4), (0, 2), (0, 4)})
-            assert ms > 0
+            rb, zb, gb, ms = s3.autotune(cache, batch=True)
+            # one direction group; 4 rows in 2D, and 4 planes of the flattened
+            # plane on this narrow 3D mesh (the batch fills the device)
+            assert (rb, zb) == ((4, 1) if dim == 2 else (0, 4))
+            assert gb == 1 and ms > 0
+        # the batch choice is recorded apart from the single-geometry one
+        assert f" batch -> ry={rb} rz={zb} ndg=1" in open(cache).read()
+        with gpu.Solver(inst) as s4:
+            assert s4.autotune(cache)[:3] == (ry, rz, ndg)
 
 
 @pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
