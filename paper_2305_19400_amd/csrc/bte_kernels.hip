@@ -1417,7 +1417,10 @@ __device__ __forceinline__ void relation_part(const Tables& t, int nb, int l, do
                                               double& dF) {
 #pragma clang fp contract(off)
   double f = 0.0, df = 0.0;
-#pragma unroll 4
+  // unrolled by 2, not 4: with constant relaxation times the inversion then
+  // fits 94 VGPRs, 5 waves per SIMD instead of 4 (the batched inversion of
+  // the 64-geometry draw measured 18 % less time)
+#pragma unroll 2
   for (int b = l; b < nb; b += LANES) {
     const double x = t.xfac[b] / T;
     const double em1 = expm1(x);
@@ -1462,7 +1465,9 @@ __device__ __forceinline__ void relation_part_tau(const Tables& t, int nb, int l
 // partials, invert the temperature relation by Newton from the current T
 // (accept-first, quadratic convergence; Sec. 2.2 and Sec. 3.2 temperature
 // update), then refresh the equilibrium intensities I0[b][P] for the next sweep.
-template <int LANES>
+// TAUT: relaxation times depend on T (their Newton relation and rate refresh
+// take registers that would cost the constant-tau kernel a wave per SIMD).
+template <int LANES, bool TAUT>
 __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables& t,
                                                  double* __restrict__ S,
                                                  double* __restrict__ T, double* __restrict__ I0,
@@ -1474,7 +1479,7 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
   const bool active = P < g.nc;
   const int Pc = active ? P : 0;
   const size_t ncp = (size_t)g.ncp;
-  const bool tau_newton = t.relax != nullptr && t.tau_weighted;
+  const bool tau_newton = TAUT && t.tau_weighted;
   CompSum Gs, Es;
   if (active) {
     // The partials of up to kChunk of this lane's bands are requested
@@ -1564,42 +1569,52 @@ __device__ __forceinline__ void temperature_body(const Geometry& g, const Tables
       }
     }
   }
+  // The step's largest Newton count, one atomic per wave: one per cell put
+  // millions of atomics on one address per iteration and doubled the
+  // batched inversion's time once the warm start made every cell iterate.
+  // Every lane of the wave is active here.
+  int itw = (active && ok) ? it : 0;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) itw = max(itw, __shfl_xor(itw, m, 64));
+  if ((threadIdx.x & 63) == 0 && itw > 0) atomicMax(&ctl->newton_max, itw);
   if (!active) return;
   if (!ok) {
     if (l == 0) atomicMin(&ctl->err_cell, P);
     return;
   }
-#pragma unroll 4
+#pragma unroll 2
   for (int b = l; b < g.nb; b += LANES)
     I0[(size_t)b * ncp + P] = equilibrium(t.Cb[b], t.xfac[b], Tc);
-  if (t.relax)
+  if constexpr (TAUT)
     for (int b = l; b < g.nb; b += LANES)
       t.relax[(size_t)b * ncp + P] = relax_rate(t.inv_tau[b], t.tau_p[b], Tc, t.tau_T0);
   if (l == 0) {
     T[P] = Tc;
     E[P] = En;
-    if (it > 0) atomicMax(&ctl->newton_max, it);
   }
 }
 
-template <int LANES>
+template <int LANES, bool TAUT>
 __global__ __launch_bounds__(256) void temperature_kernel(Geometry g, Tables t,
                                                           double* __restrict__ S,
                                                           double* __restrict__ T,
                                                           double* __restrict__ I0,
                                                           double* __restrict__ E, Control* ctl) {
   if (step_done(ctl)) return;
-  temperature_body<LANES>(g, t, S, T, I0, E, ctl, blockIdx.x);
+  temperature_body<LANES, TAUT>(g, t, S, T, I0, E, ctl, blockIdx.x);
 }
 
 hipError_t launch_temperature(hipStream_t stream, const Geometry& g, const Tables& t,
                               double* S, double* T, double* I0, double* E, Control* ctl) {
   const int cells_per_block = temp_cells_per_block(g.nb);
   const dim3 grid((g.nc + cells_per_block - 1) / cells_per_block);
-  if (temp_lanes(g.nb) == 4)
-    hipLaunchKernelGGL(temperature_kernel<4>, grid, dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
+  const bool four = temp_lanes(g.nb) == 4;
+  if (t.relax)
+    hipLaunchKernelGGL((four ? temperature_kernel<4, true> : temperature_kernel<8, true>), grid,
+                       dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
   else
-    hipLaunchKernelGGL(temperature_kernel<8>, grid, dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
+    hipLaunchKernelGGL((four ? temperature_kernel<4, false> : temperature_kernel<8, false>), grid,
+                       dim3(256), 0, stream, g, t, S, T, I0, E, ctl);
   return hipGetLastError();
 }
 
@@ -2000,10 +2015,12 @@ __global__ __launch_bounds__(256) void batch_temperature_kernel(const BatchCtx* 
   // could otherwise alias the context array and force them to be reloaded
   const Geometry g = c.sp64.g;
   const Tables t = c.sp64.t;
+  // a batch takes constant relaxation times only (bte_batch_create refuses a
+  // temperature law)
   if (temp_lanes(g.nb) == 4)
-    temperature_body<4>(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
+    temperature_body<4, false>(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
   else
-    temperature_body<8>(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
+    temperature_body<8, false>(g, t, c.S, c.T, c.I0, c.E, c.ctl, blk - c.cell_block0);
 }
 
 __global__ __launch_bounds__(kReduceBlock) void batch_control_kernel(BatchCtx* ctxs) {
