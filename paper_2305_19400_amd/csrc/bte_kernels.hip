@@ -193,6 +193,15 @@ constexpr int kPastEnd = 0x7ffffff0;
 #ifndef BTE_SLAB_STORE_AUX
 #define BTE_SLAB_STORE_AUX 2
 #endif
+// The step-start field I^n is read once per sweep, each value by its own
+// cell's lane, so its loads are non-temporal too: they then do not displace
+// the current iterate's rows, which neighbouring tiles re-read as halos
+// (measured: c3 sweeps 6 % faster in FP32 and 2 % in FP64, c2 FP32 1 %, c4
+// FP32 0.6 %; making the iterate's own loads non-temporal as well was 9-11 %
+// slower).
+#ifndef BTE_STEP_LOAD_AUX
+#define BTE_STEP_LOAD_AUX 2
+#endif
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const void* base, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufferWord3);
@@ -240,6 +249,19 @@ __device__ __forceinline__ double buf_load_raw<double>(__amdgpu_buffer_rsrc_t r,
 template <>
 __device__ __forceinline__ float buf_load_raw<float>(__amdgpu_buffer_rsrc_t r, int voff) {
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, BTE_SLAB_LOAD_AUX));
+}
+
+// A value of the step-start field I^n (non-temporal load).
+template <typename Real>
+__device__ __forceinline__ Real buf_load_step(__amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ double buf_load_step<double>(__amdgpu_buffer_rsrc_t r, int voff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, BTE_STEP_LOAD_AUX);
+  return __longlong_as_double(((long long)v[1] << 32) | (unsigned int)v[0]);
+}
+template <>
+__device__ __forceinline__ float buf_load_step<float>(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, BTE_STEP_LOAD_AUX));
 }
 
 template <typename Real>
@@ -530,7 +552,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       k[j] = buf_load_raw<Real>(rk, vr[j]);
-      n[j] = buf_load_raw<Real>(rn, vr[j]);
+      n[j] = buf_load_step<Real>(rn, vr[j]);
     }
   };
   if constexpr (kPrefetch)
@@ -813,7 +835,7 @@ __device__ __forceinline__ void walk3d_body(const SweepParams<Real>& p, const in
 #pragma unroll
       for (int q = 0; q < RZ; ++q) {
         k[j][q] = buf_load_raw<Real>(rk, off[j][q]);
-        n[j][q] = buf_load_raw<Real>(rn, off[j][q]);
+        n[j][q] = buf_load_step<Real>(rn, off[j][q]);
       }
   };
   if constexpr (kPrefetch)
@@ -1143,7 +1165,7 @@ __device__ __forceinline__ void flat3d_body(const SweepParams<Real>& p, const in
 #pragma unroll
       for (int k = 0; k < RZ; ++k) {
         rk_v[k] = buf_load_raw<Real>(rk, vc[k]);
-        rn_v[k] = buf_load_raw<Real>(rn, vc[k]);
+        rn_v[k] = buf_load_step<Real>(rn, vc[k]);
       }
       // the halo: upwind cells outside the tile (masked to the lanes that
       // need them)
