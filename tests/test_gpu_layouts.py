@@ -330,3 +330,44 @@ def test_default_layouts(gpu, monkeypatch):
         with gpu.Solver(meshes[which], precision=prec) as sol:
             lay = sol.sweep_layout()
         assert (lay["kind"], lay["ry"], lay["rz"]) == (kind, ry, rz), (which, prec, lay)
+
+
+@pytest.mark.parametrize("precision", [I.PRECISION_FP64, I.PRECISION_FP32_MIXED])
+def test_2d_padded_rows_in_copies_and_checkpoint(gpu, precision):
+    """2D slabs pad each row to a 128-byte line (45 cells: 48 in FP64, 64 in
+    FP32 storage), while intensity(), set_fields and the checkpoint use the
+    dense [b][d][P] order.  Six steps in one go equal three, a checkpoint
+    restored into a fresh context and three more, bit for bit; the
+    checkpoint's intensity section is intensity() in storage format; the
+    intensity and temperature re-imported through set_fields come back (FP64:
+    bit for bit, and the next steps take the same sweeps; FP32 storage
+    re-rounds I - Iref, so to 1e-12)."""
+    inst = I.strip_2d(45, 23, 2, 8, 4, seed=41, strip_cells=6, nsteps=6)
+    nb, nd, nc = inst.n_bands, inst.n_dirs, inst.n_cells
+    announce(f"2D padded rows, precision {precision}")
+    with gpu.Solver(inst, precision=precision) as a:
+        a.step(3)
+        state = a.get_state()
+        Ia3, Ta3 = a.intensity(), a.temperature()
+        sa = a.step(3)
+        Ta, Ia = a.temperature(), a.intensity()
+    st = gpu.parse_state(state)
+    dense = st["I"].astype(np.float64)
+    if precision == I.PRECISION_FP32_MIXED:
+        dense = st["Iref"][:, None, None] + dense
+    assert np.array_equal(dense.reshape(Ia3.shape), Ia3)
+    with gpu.Solver(inst, precision=precision) as b:
+        b.set_state(state)
+        assert np.array_equal(b.intensity(), Ia3)
+        assert b.step(3) == sa
+        assert np.array_equal(b.temperature(), Ta) and np.array_equal(b.intensity(), Ia)
+    with gpu.Solver(inst, precision=precision) as c:
+        c.set_fields(Ia3, Ta3)
+        assert np.array_equal(c.temperature(), Ta3)
+        if precision == I.PRECISION_FP64:
+            assert np.array_equal(c.intensity(), Ia3)
+            sc = c.step(3)
+            assert [s["inner"] for s in sc] == [s["inner"] for s in sa]
+        else:
+            assert float(np.max(np.abs(c.intensity() - Ia3) / Ia3)) <= 1e-12
+    assert Ia3.size == nb * nd * nc
