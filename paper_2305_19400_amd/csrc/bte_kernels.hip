@@ -196,9 +196,9 @@ constexpr int kPastEnd = 0x7ffffff0;
 // The step-start field I^n is read once per sweep, each value by its own
 // cell's lane, so its loads are non-temporal too: they then do not displace
 // the current iterate's rows, which neighbouring tiles re-read as halos
-// (measured: c3 sweeps 6 % faster in FP32 and 2 % in FP64, c2 FP32 1 %, c4
-// FP32 0.6 %; making the iterate's own loads non-temporal as well was 9-11 %
-// slower).
+// (measured on 400 directions x 55 band entries: 64^3 sweeps 6 % faster in
+// FP32 and 2 % in FP64, 128 x 128 FP32 1 %, 96^3 FP32 0.6 %; making the
+// iterate's own loads non-temporal as well was 9-11 % slower).
 #ifndef BTE_STEP_LOAD_AUX
 #define BTE_STEP_LOAD_AUX 2
 #endif
