@@ -88,8 +88,11 @@ enum bte_tdef { BTE_T_TAU_WEIGHTED = 0, BTE_T_ENERGY = 1 };
 /* Mesh, walls and initial temperature (host arrays). */
 typedef struct {
   int dim;                  /* 2 or 3 */
-  int n[3];                 /* cells per axis; n[2] = 1 in 2D; N_c = n[0] n[1] n[2] at most
-                               268435423 (an FP64 slab stays within 32-bit byte offsets) */
+  int n[3];                 /* cells per axis; n[2] = 1 in 2D; N_c = n[0] n[1] n[2].  The
+                               padded count -- 2D: n[0] rounded up to 32 cells (16 with
+                               FP64 storage) times n[1]; 3D: N_c rounded up to 64 -- is at
+                               most 268435424 (an FP64 slab stays within 32-bit byte
+                               offsets); BTE_E_INVAL above */
   double h[3];              /* cell size per axis [m]; h[2] ignored in 2D */
   int wall[6];              /* bte_wall per side; z sides ignored in 2D */
   const double* wall_T[6];  /* per-face temperature [K] of isothermal walls, else NULL */

@@ -95,6 +95,12 @@ def test_validation_rejects_bad_inputs_without_device():
     huge = base.copy(dim=3, n=[700, 700, 700], h=[1e-8, 1e-8, 1e-8])
     rc, msg = _create_status(huge)
     assert rc == bte.BTE_E_INVAL and "too many cells" in msg
+    # a 2D mesh whose cells fit but whose rows, padded to a 128-byte line
+    # (16383 -> 16384 cells), do not
+    padded = base.copy(n=[16383, 16384, 1])
+    for prec in (bte.BTE_FP64, bte.BTE_FP32_MIXED):
+        rc, msg = _create_status(padded, precision=prec)
+        assert rc == bte.BTE_E_INVAL and "with padding" in msg, msg
     # wall tables past 32-bit offsets: 4 band entries x 10^8 faces of a z side
     wide = base.copy(dim=3, n=[10000, 10000, 2], h=[1e-8, 1e-8, 1e-8])
     rc, msg = _create_status(wide)
