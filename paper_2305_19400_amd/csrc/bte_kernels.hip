@@ -545,15 +545,20 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
   // measured neutral and each direction loads its own rows.
   constexpr bool kPrefetch = Storage<Real>::kDeviation;
   Real rk_v[RY], rn_v[RY];
-  auto load_rows = [](const Real* slab_k, const Real* slab_n, int bytes, const int (&vr)[RY],
-                      Real (&k)[RY], Real (&n)[RY]) {
+  // The first sweep of a step (and every forward-Euler update) reads I^n as
+  // its iterate: then I^n is loaded once (measured: forward-Euler sweeps of
+  // 120 x 120 cells, 20 directions x 55 band entries, 4.6 % faster; 128 x 128
+  // cells, 400 x 55 over whole steps 0.4 % in FP64 and 0.9 % in FP32).
+  const bool same = Inb == Ikb;
+  auto load_rows = [same](const Real* slab_k, const Real* slab_n, int bytes,
+                          const int (&vr)[RY], Real (&k)[RY], Real (&n)[RY]) {
     const auto rk = slab_rsrc(slab_k, bytes);
     const auto rn = slab_rsrc(slab_n, bytes);
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-      k[j] = buf_load_raw<Real>(rk, vr[j]);
-      n[j] = buf_load_step<Real>(rn, vr[j]);
-    }
+    for (int j = 0; j < RY; ++j) k[j] = buf_load_raw<Real>(rk, vr[j]);
+    if (!same)
+#pragma unroll
+      for (int j = 0; j < RY; ++j) n[j] = buf_load_step<Real>(rn, vr[j]);
   };
   if constexpr (kPrefetch)
     if (nrows > 0 && d_begin < d_end)
@@ -609,7 +614,7 @@ __device__ __forceinline__ void walk2d_body(const SweepParams<Real>& p, const in
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       ik[j] = rk_v[j];
-      in[j] = rn_v[j];
+      in[j] = same ? rk_v[j] : rn_v[j];
       if constexpr (SHIFT) ik[j] += sh[j];
     }
     const A c0 = static_cast<A>(cf.c[0]), c1 = static_cast<A>(cf.c[1]);
